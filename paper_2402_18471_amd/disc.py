@@ -1,0 +1,168 @@
+"""Seeded synthetic protoplanetary-disc inputs for the coagulation update.
+
+This module only makes inputs: per-cell gas state, dust velocities (standing in
+for the dust dynamics solver, whose output the collision kernel reads) and an
+initial size distribution.  It contains none of the coagulation method's
+arithmetic, and it is the only code that the GPU library's tests and the CPU
+oracle's tests both use.
+
+Disc shape follows the paper's transition-disc test (Sec. 8, table `params`):
+Sigma_g = Sigma_0 R_au^-1 exp[-(5/R_au)^10], Sigma_0 = 250 g cm^-2, M_* = 1 M_sun,
+mu = 2.4; vertically isothermal T = 150 K (R/au)^-1/2; Gaussian rho_g(Z) with
+H/R = 0.05; MRN initial dust (n(s) ~ s^-3.5) up to 1 micron at dust-to-gas 0.01.
+No public dataset is involved; every random draw is seeded.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# physical constants (CGS)
+K_B = 1.380649e-16
+M_H = 1.6735575e-24
+G_GRAV = 6.67430e-8
+M_SUN = 1.98847e33
+AU = 1.495978707e13
+YEAR = 3.15576e7
+SIGMA_H2 = 2.0e-15          # H2 collision cross-section for the molecular mean free path
+
+SEED_ALPHA = 240218471
+SEED_FD = 240218472
+
+
+@dataclass
+class DiscConfig:
+    name: str
+    n_r: int
+    n_z: int
+    n_bins: int
+    s_min: float                 # cm
+    s_max: float                 # cm
+    alpha: float | tuple = 1e-3  # scalar, or (lo, hi) log-uniform per radial ring
+    v_frag: float = 100.0        # cm/s
+    steps: int = 1000
+    dt: float = 10.0 * YEAR      # s per coagulation call
+    rho_m: float = 1.67          # grain material density, g cm^-3
+    r_in_au: float = 5.0
+    r_out_au: float = 100.0
+    z_max_h: float = 3.0
+    h_over_r: float = 0.05
+    mu: float = 2.4
+    sigma0: float = 250.0
+    dust_to_gas: float = 0.01
+    s_mrn_max: float = 1.0e-4    # cm
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_cells(self) -> int:
+        return self.n_r * self.n_z
+
+
+CONFIGS = {
+    # 64 (R, 5-100 au) x 32 (Z, 0-3H) cells x 100 bins (0.1 um - 10 cm), plain FP64
+    "disc64x32_n100": DiscConfig("disc64x32_n100", 64, 32, 100, 1e-5, 10.0, 1e-3, 100.0, 1000),
+    # 256 x 128 cells x 150 bins, v_frag = 10 m/s (FP64 vs split-BF16)
+    "disc256x128_n150": DiscConfig("disc256x128_n150", 256, 128, 150, 1e-5, 10.0, 1e-3, 1000.0, 1000),
+    # adjoint case: the 64 x 32 x 100 disc over 200 steps
+    "disc64x32_n100_adj": DiscConfig("disc64x32_n100_adj", 64, 32, 100, 1e-5, 10.0, 1e-3, 100.0, 200),
+    # large: 512 x 256 x 200 bins (0.1 um - 1 m), alpha log-uniform per ring
+    "disc512x256_n200": DiscConfig("disc512x256_n200", 512, 256, 200, 1e-5, 100.0, (1e-4, 1e-2), 300.0, 500),
+}
+
+
+def scaled(cfg: DiscConfig, n_r: int, n_z: int, n_bins: int | None = None) -> DiscConfig:
+    """Same physics on a coarser cell grid (and optionally fewer bins)."""
+    d = dict(cfg.__dict__)
+    d.update(name=f"{cfg.name}_sub{n_r}x{n_z}", n_r=n_r, n_z=n_z)
+    if n_bins is not None:
+        d["n_bins"] = n_bins
+    return DiscConfig(**d)
+
+
+def make_cells(cfg: DiscConfig):
+    """Per-cell gas state, cell index c = i_r * n_z + i_z (radius-major).
+
+    Returns dict with R, Z (cm), Sigma_g, and the seven per-cell inputs of the
+    collision kernel: T, rho_g, c_s, Omega, H, nu_mol, alpha."""
+    r_au = np.geomspace(cfg.r_in_au, cfg.r_out_au, cfg.n_r)
+    R = r_au * AU
+    H = cfg.h_over_r * R
+    zfrac = (np.arange(cfg.n_z) + 0.5) / cfg.n_z * cfg.z_max_h
+    Rg, Zh = np.meshgrid(R, zfrac, indexing="ij")
+    Hg = cfg.h_over_r * Rg
+    Z = Zh * Hg
+    r_au_g = Rg / AU
+    sigma_g = cfg.sigma0 / r_au_g * np.exp(-(5.0 / r_au_g) ** 10)
+    rho_g = sigma_g / (np.sqrt(2.0 * np.pi) * Hg) * np.exp(-0.5 * Zh ** 2)
+    T = 150.0 * r_au_g ** -0.5
+    c_s = np.sqrt(K_B * T / (cfg.mu * M_H))
+    Omega = np.sqrt(G_GRAV * M_SUN / (Rg ** 2 + Z ** 2) ** 1.5)
+    # molecular viscosity nu_mol = v_th lambda / 2 with lambda = mu m_H / (rho_g sigma_H2)
+    v_th = np.sqrt(8.0 / np.pi) * c_s
+    lam = cfg.mu * M_H / (rho_g * SIGMA_H2)
+    nu_mol = 0.5 * v_th * lam
+    if isinstance(cfg.alpha, tuple):
+        rng = np.random.default_rng(SEED_ALPHA)
+        lo, hi = np.log10(cfg.alpha[0]), np.log10(cfg.alpha[1])
+        ring = 10.0 ** rng.uniform(lo, hi, size=cfg.n_r)
+        alpha = np.repeat(ring[:, None], cfg.n_z, axis=1)
+    else:
+        alpha = np.full_like(T, float(cfg.alpha))
+    flat = lambda a: np.ascontiguousarray(a.reshape(-1), dtype=np.float64)
+    return dict(R=flat(Rg), Z=flat(Z), Sigma_g=flat(sigma_g), T=flat(T), rho_g=flat(rho_g),
+                c_s=flat(c_s), Omega=flat(Omega), H=flat(Hg), nu_mol=flat(nu_mol), alpha=flat(alpha))
+
+
+def make_dust_velocities(cfg: DiscConfig, cells, s):
+    """Dust velocities [C][N][3] (v_R, v_phi - v_K, v_Z) in cm/s.
+
+    A stand-in for the dynamics solver: textbook radial drift, azimuthal lag and
+    settling driven by the gas pressure gradient of this disc, with the
+    midplane Epstein Stokes number (pi/2) rho_m s / Sigma_g raised with height
+    as the gas thins.  The azimuthal component is stored relative to the local
+    Keplerian speed (relative velocities do not depend on the frame)."""
+    R, Z, H = cells["R"], cells["Z"], cells["H"]
+    c_s, sig = cells["c_s"], cells["Sigma_g"]
+    s = np.asarray(s, dtype=np.float64)
+    v_k = np.sqrt(G_GRAV * M_SUN / R)
+    r_au = R / AU
+    dlnp = -2.5 + 10.0 * (5.0 / r_au) ** 10 + (Z / H) ** 2
+    eta = -0.5 * (c_s / v_k) ** 2 * dlnp
+    st = (0.5 * np.pi * cfg.rho_m * s[None, :] / sig[:, None]) * np.exp(0.5 * (Z / H)[:, None] ** 2)
+    omega_k = v_k / R
+    v = np.empty((R.shape[0], s.shape[0], 3))
+    v[:, :, 0] = -2.0 * (eta * v_k)[:, None] * st / (1.0 + st ** 2)
+    v[:, :, 1] = -(eta * v_k)[:, None] / (1.0 + st ** 2)
+    v[:, :, 2] = -(omega_k * Z)[:, None] * st / (1.0 + st ** 2)
+    return np.ascontiguousarray(v)
+
+
+def make_initial_rho(cfg: DiscConfig, cells, s):
+    """MRN start: mass per bin ~ s^(1/2) for s <= s_mrn_max, zero above,
+    normalised to dust_to_gas * rho_g in every cell.  [C][N] g cm^-3."""
+    s = np.asarray(s, dtype=np.float64)
+    shape = np.where(s <= cfg.s_mrn_max * (1 + 1e-12), np.sqrt(s), 0.0)
+    if not shape.any():             # grid starts above the MRN range: all in bin 0
+        shape[0] = 1.0
+    shape = shape / shape.sum()
+    rho = cfg.dust_to_gas * cells["rho_g"][:, None] * shape[None, :]
+    return np.ascontiguousarray(rho)
+
+
+def make_disc(cfg: DiscConfig, s):
+    """Everything one coagulation call needs, for radii s [N] of the bins."""
+    cells = make_cells(cfg)
+    v = make_dust_velocities(cfg, cells, s)
+    rho = make_initial_rho(cfg, cells, s)
+    v_frag = np.full(cfg.n_cells, float(cfg.v_frag))
+    return dict(cells=cells, v_dust=v, v_frag=v_frag, rho=rho, dt=cfg.dt)
+
+
+def subset_cells(disc, idx):
+    """Cells idx of a disc (same arrays, fewer cells)."""
+    idx = np.asarray(idx)
+    cells = {k: np.ascontiguousarray(v[idx]) for k, v in disc["cells"].items()}
+    return dict(cells=cells, v_dust=np.ascontiguousarray(disc["v_dust"][idx]),
+                v_frag=np.ascontiguousarray(disc["v_frag"][idx]),
+                rho=np.ascontiguousarray(disc["rho"][idx]), dt=disc["dt"])
