@@ -1,0 +1,202 @@
+/*
+ * coag.h -- C ABI of libcoag, the MI355X (gfx950) coagulation-fragmentation
+ * update of Robinson, Booth & Owen, "Introducing cuDisc" (Sec. 5, "Dust growth
+ * and fragmentation"; sub-cycling rule of Sec. 6, "Code structure").
+ *
+ * Each (R, Z) cell evolves its binned grain-size distribution rho[cell][k]
+ * (g cm^-3 per mass bin) under the Smoluchowski equation with coagulation,
+ * cratering/fragmentation and power-law fragments, independently of every
+ * other cell.  Four calls make up the path:
+ *
+ *   coag_rates          pair rates  Kc = w K p_coag,  Kf = w K p_frag
+ *   coag_rhs            drho/dt  (eq. `smol`)
+ *   coag_step           sub-cycled Bogacki-Shampine 3(2) over dt
+ *   coag_step_backward  adjoint of a frozen step sequence
+ *
+ * Conventions (all calls):
+ *   - Pointers marked DEVICE are device pointers on the HIP device that was
+ *     current at coag_create; they are owned by the caller, contiguous,
+ *     row-major, FP64 unless stated.  HOST pointers are read during the call.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work is
+ *     enqueued on it; no call synchronises the host, so outputs are ready only
+ *     after the stream is synchronised.
+ *   - Pairs are packed: p(i, j) = i (i + 1) / 2 + j for j <= i (i is the
+ *     heavier grain); P = N (N + 1) / 2.
+ *   - Return value: COAG_OK, or a negative COAG_E* code for an error found on
+ *     the host before anything is launched (nothing is written then); the
+ *     message is in coag_last_error().  Failures inside a cell are reported in
+ *     that cell's `status` and never stop other cells.
+ *   - A context is bound to one device and is not thread-safe; calls that
+ *     overlap on the same context must not share the context's workspace
+ *     (use one context per stream).
+ *   - CGS units throughout.
+ */
+#ifndef COAG_H
+#define COAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct coag_ctx coag_ctx;
+
+enum {
+    COAG_OK = 0,
+    COAG_EINVAL = -1,     /* bad argument (null pointer, size, grid, tolerance) */
+    COAG_ENOMEM = -2,     /* device or host allocation failed */
+    COAG_EHIP = -3,       /* a HIP runtime call failed */
+    COAG_ENOTSUP = -4     /* combination not implemented */
+};
+
+/* per-cell status written by coag_step */
+enum {
+    COAG_CELL_OK = 0,
+    COAG_CELL_HMIN = 1,       /* step size fell below h_min_rel * dt */
+    COAG_CELL_MAXSUB = 2,     /* max_sub attempts used before reaching dt */
+    COAG_CELL_NONFINITE = 3   /* a state or error estimate became NaN/Inf */
+};
+
+/* Two-bin split of a product mass M between l(M) and u(M) = l + 1 (eqs.
+   `Cijk`, `Rijk`, eps = (m_u - M) / (m_u - m_l)):
+   MASS   : mass eps*M to l and (1-eps)*M to u (the coefficients read as mass
+            fractions, as the text states);
+   NUMBER : one particle split by number, mass eps*m_l to l, (1-eps)*m_u to u. */
+enum { COAG_SPLIT_MASS = 0, COAG_SPLIT_NUMBER = 1 };
+
+/* arithmetic of the gain/loss contraction inside coag_step */
+enum { COAG_PREC_FP64 = 0, COAG_PREC_SPLIT_BF16 = 1 };
+
+/* step-size modes of coag_step */
+enum { COAG_ADAPTIVE = 0, COAG_FIXED = 1, COAG_REPLAY = 2 };
+
+/* Mass grid and collision-outcome parameters (Sec. 5).  HOST arrays, copied
+   by coag_create.  m strictly increasing; m_edge[k] < m[k] < m_edge[k+1]
+   (bin edges, used by the fragment distribution eq. `Nijk`); s = grain radius
+   of each bin (cm).  rho_m: grain material density; eta: fragment power law
+   n(m) ~ m^-eta (eq. `fragdist`, eta != 2); chi: excavated mass in units of
+   the impactor mass (eq. `fragrem`, chi > 0); split: COAG_SPLIT_*. */
+typedef struct {
+    int32_t n_bins;           /* N, 2 <= N <= 1023 */
+    int32_t split;
+    const double *m;          /* [N]   HOST */
+    const double *m_edge;     /* [N+1] HOST */
+    const double *s;          /* [N]   HOST */
+    double rho_m, eta, chi;
+} coag_grid;
+
+/* Per-cell gas state, each a DEVICE array [C]: temperature T (K), gas density
+   rho_g, isothermal sound speed c_s, Keplerian angular speed Omega, gas scale
+   height H, molecular kinematic viscosity nu_mol, turbulence parameter alpha
+   (alpha = 0 switches turbulent relative velocities off). */
+typedef struct {
+    const double *T, *rho_g, *c_s, *Omega, *H, *nu_mol, *alpha;
+} coag_cells;
+
+/* Step control (Sec. 5: rtol = 1e-2, atol = 1e-10 * sum_k rho_k by default).
+   mode: COAG_ADAPTIVE / COAG_FIXED / COAG_REPLAY.  max_sub: cap on attempted
+   sub-steps per cell per call (ADAPTIVE), and the row length of h_log.
+   prec: COAG_PREC_*.  renorm: non-zero rescales each cell's state after the
+   call so that its total mass equals the total at entry. */
+typedef struct {
+    double rtol, atol_rel, h_min_rel;
+    int32_t max_sub, mode, prec, renorm;
+} coag_tol;
+
+/* ------------------------------------------------------------------------- */
+
+/* Log-spaced mass grid on the HOST (no device work).  N bins whose outer
+   edges are lo and hi (grain radius in cm if by_mass == 0, else mass in g),
+   edges lo (hi/lo)^(k/N), centres at the log midpoints lo (hi/lo)^((k+1/2)/N),
+   m = (4 pi / 3) rho_m s^3.  Writes m[N], m_edge[N+1], s[N] (HOST, caller-
+   owned).  Reading of Sec. 8: with it, the paper's 100 bins over
+   0.1 um - 0.5 cm and 135 bins over 0.1 um - 20 cm both have
+   m_{n+1}/m_n = 1.38.  Returns COAG_EINVAL for N < 2, lo <= 0, hi <= lo,
+   rho_m <= 0 or a null pointer. */
+int coag_mass_grid(int32_t n_bins, double lo, double hi, int32_t by_mass, double rho_m,
+                   double *m, double *m_edge, double *s);
+
+/* Create a context on the current HIP device: validates the grid and builds
+   on the device, once, the redistribution tables of the gain term (where the
+   products of each pair go: coagulation split, remnant split, top fragment
+   bin and fragment mass, eqs. `Cijk`, `Rijk`, `fragrem`, `Nijk`).  The
+   context owns those tables and its workspaces; *out receives it.
+   Errors: COAG_EINVAL (bad grid), COAG_ENOMEM, COAG_EHIP. */
+int coag_create(const coag_grid *grid, coag_ctx **out);
+
+/* Free a context and everything it owns (NULL is accepted).  Synchronises the
+   device first so that no queued work still uses the context. */
+void coag_destroy(coag_ctx *ctx);
+
+/* Last error message of this context (or of the last failed coag_create /
+   coag_mass_grid when ctx is NULL); "" if none.  Valid until the next call. */
+const char *coag_last_error(const coag_ctx *ctx);
+
+/* Pair rates for C cells (Sec. 5, eqs. `kernel`, `vbrown`, `OCVrel`,
+   `p_frag`; Stokes number from the Epstein stopping time, eq. `t_stop`, times
+   Omega; Re = alpha c_s H / nu_mol as in Sec. 7.1).
+     v_dust [C][N][3] DEVICE   dust velocities from the dynamics solver
+     v_frag [C]       DEVICE   fragmentation velocity
+     Kc, Kf [C][P]    DEVICE   out: w K_ij p_coag,ij and w K_ij p_frag,ij with
+                               w = 1/2 for i = j (the halving the gain term asks for)
+   Errors: COAG_EINVAL (C < 0, null pointer). */
+int coag_rates(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
+               const double *v_frag, double *Kc, double *Kf, void *stream);
+
+/* Right-hand side of eq. `smol` for C cells:
+     drho_k = sum_{i, j<=i} n_i n_j [Kc (m_i+m_j) C_ijk + Kf (m_rem R_ijk + m_frag F_ijk)]
+              - m_k n_k sum_i K_ik n_i (p_c + p_f),      n = rho / m,
+   fragments distributed per top bin (the accumulation of Rafikov et al. 2020).
+     rho     [C][N] DEVICE in;   Kc, Kf [C][P] DEVICE in;   drho_dt [C][N] DEVICE out.
+   Errors: COAG_EINVAL. */
+int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, const double *Kf,
+             double *drho_dt, void *stream);
+
+/* Advance every cell by dt (Sec. 5 closing paragraph; Sec. 6 sub-cycling).
+   BS3(2) with first-same-as-last reuse:
+     k1 = f(y), k2 = f(y + h/2 k1), k3 = f(y + 3h/4 k2),
+     y+ = y + h (2/9 k1 + 1/3 k2 + 4/9 k3),   k4 = f(y+),
+     e  = h (-5/72 k1 + 1/12 k2 + 1/9 k3 - 1/8 k4).
+   ADAPTIVE: err = max_k |e_k| / (atol + rtol max(|y_k|, |y+_k|)), atol =
+   atol_rel * sum_k y_k at entry; accept iff err <= 1 and no y+_k < -atol; step
+   factor clamp(0.9 err^(-1/3), 0.2, 5) (5 if err = 0), 0.5 after a rejection
+   caused only by a negative state; the final step is clipped to land on dt and
+   a clipped accepted step leaves h unchanged.  FIXED: nsub[c] equal steps of
+   dt/nsub[c].  REPLAY: nsub[c] steps of the sizes h_log[c][0..nsub[c]).
+     rho     [C][N]        DEVICE in/out
+     Kc, Kf  [C][P]        DEVICE in (from coag_rates, or any kernel)
+     h       [C]           DEVICE in/out (ADAPTIVE): h <= 0 on entry starts with dt;
+                           on exit the controller's next (unclipped) step size
+     nsub    [C] int32     DEVICE out (ADAPTIVE: accepted steps) or in (FIXED, REPLAY)
+     nrej    [C] int32     DEVICE out, rejected attempts (may be NULL)
+     h_log   [C][max_sub]  DEVICE out (ADAPTIVE, FIXED: accepted step sizes; may be
+                           NULL) or in (REPLAY, required)
+     status  [C] int32     DEVICE out, COAG_CELL_*
+   Errors: COAG_EINVAL (null pointer, C < 0, dt <= 0, rtol <= 0, max_sub < 1,
+   unknown mode or precision), COAG_ENOMEM. */
+int coag_step(coag_ctx *ctx, int64_t C, double *rho, const double *Kc, const double *Kf,
+              double dt, double *h, const coag_tol *tol, int32_t *nsub, int32_t *nrej,
+              double *h_log, int32_t *status, void *stream);
+
+/* Discrete adjoint of coag_rates + coag_step over a frozen step sequence
+   (nsub[c] accepted steps of sizes h_log[c][:], as a REPLAY or FIXED call
+   reproduces them).  With J a scalar of the final state and g_out = dJ/drho_end:
+     g_in    [C][N] DEVICE out   dJ/drho at the start of the call
+     g_alpha [C]    DEVICE out   dJ/dalpha_c (through v_turb and Re)
+     g_vfrag [C]    DEVICE out   dJ/dv_frag,c (through p_frag)
+   Inputs rho_in [C][N], cells, v_dust, v_frag as for coag_rates; h_log
+   [C][log_stride], nsub [C] DEVICE.  The stage states are recomputed from
+   rho_in.  prec: COAG_PREC_* of the contraction used in the recomputation and
+   the reverse sweep.  Errors: COAG_EINVAL, COAG_ENOMEM. */
+int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coag_cells *cells,
+                       const double *v_dust, const double *v_frag, const double *h_log,
+                       int32_t log_stride, const int32_t *nsub, const double *g_out,
+                       double *g_in, double *g_alpha, double *g_vfrag, int32_t prec,
+                       void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COAG_H */

@@ -1,0 +1,92 @@
+"""ctypes binding of libcoag (include/coag.h): argument marshalling only.
+
+Every numerical step runs in the HIP kernels of the library; this module
+checks tensor shapes, dtypes and devices, passes raw device pointers and the
+current torch stream, and turns error codes into exceptions.  It refuses to
+run without the compiled library (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libcoag.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "coag.h")
+
+COAG_OK, COAG_EINVAL, COAG_ENOMEM, COAG_EHIP, COAG_ENOTSUP = 0, -1, -2, -3, -4
+CELL_OK, CELL_HMIN, CELL_MAXSUB, CELL_NONFINITE = 0, 1, 2, 3
+SPLIT_MASS, SPLIT_NUMBER = 0, 1
+PREC_FP64, PREC_SPLIT_BF16 = 0, 1
+ADAPTIVE, FIXED, REPLAY = 0, 1, 2
+
+_dp = ct.POINTER(ct.c_double)
+_vp = ct.c_void_p
+
+
+class Grid(ct.Structure):
+    _fields_ = [("n_bins", ct.c_int32), ("split", ct.c_int32), ("m", _dp), ("m_edge", _dp),
+                ("s", _dp), ("rho_m", ct.c_double), ("eta", ct.c_double), ("chi", ct.c_double)]
+
+
+class Cells(ct.Structure):
+    _fields_ = [(k, _vp) for k in ("T", "rho_g", "c_s", "Omega", "H", "nu_mol", "alpha")]
+
+
+class Tol(ct.Structure):
+    _fields_ = [("rtol", ct.c_double), ("atol_rel", ct.c_double), ("h_min_rel", ct.c_double),
+                ("max_sub", ct.c_int32), ("mode", ct.c_int32), ("prec", ct.c_int32),
+                ("renorm", ct.c_int32)]
+
+
+class CoagError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libcoag error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libcoag.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError(f"{LIBPATH} is missing: build it with "
+                           "`python -m paper_2402_18471_amd.build` (hipcc, gfx950)")
+    lib = ct.CDLL(LIBPATH)
+    i32, i64 = ct.c_int32, ct.c_int64
+    P = ct.POINTER
+    sig = {
+        "coag_mass_grid": (ct.c_int, [i32, ct.c_double, ct.c_double, i32, ct.c_double, _dp, _dp, _dp]),
+        "coag_create": (ct.c_int, [P(Grid), P(_vp)]),
+        "coag_destroy": (None, [_vp]),
+        "coag_last_error": (ct.c_char_p, [_vp]),
+        "coag_rates": (ct.c_int, [_vp, i64, P(Cells), _vp, _vp, _vp, _vp, _vp]),
+        "coag_rhs": (ct.c_int, [_vp, i64, _vp, _vp, _vp, _vp, _vp]),
+        "coag_step": (ct.c_int, [_vp, i64, _vp, _vp, _vp, ct.c_double, _vp, P(Tol), _vp, _vp,
+                                 _vp, _vp, _vp]),
+        "coag_step_backward": (ct.c_int, [_vp, i64, _vp, P(Cells), _vp, _vp, _vp, i32, _vp, _vp,
+                                          _vp, _vp, _vp, i32, _vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype, f.argtypes = res, args
+    _lib = lib
+    return lib
+
+
+def header_symbols():
+    """Function names declared in include/coag.h."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(coag_[a-z_]+)\s*\(", src)))
+
+
+def check(rc, ctx=None):
+    if rc != COAG_OK:
+        msg = load().coag_last_error(ctx)
+        raise CoagError(rc, msg.decode() if msg else "")

@@ -1,0 +1,160 @@
+"""Python face of libcoag with the C ABI's names (coag_mass_grid, coag_create,
+coag_rates, coag_rhs, coag_step, coag_step_backward).
+
+Tensors are torch CUDA (HIP) tensors, float64 (int32 for counters), contiguous;
+torch supplies device memory and the current stream, nothing else.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+CELL_KEYS = ("T", "rho_g", "c_s", "Omega", "H", "nu_mol", "alpha")
+
+
+def coag_mass_grid(n_bins, lo, hi, by_mass=False, rho_m=1.67):
+    """Host mass grid: N bins with outer edges lo, hi (radius in cm, or mass in
+    g if by_mass).  Returns numpy (m, m_edge, s)."""
+    m, me, s = np.empty(n_bins), np.empty(n_bins + 1), np.empty(n_bins)
+    dp = lambda a: a.ctypes.data_as(L._dp)
+    L.check(L.load().coag_mass_grid(n_bins, lo, hi, 1 if by_mass else 0, rho_m, dp(m), dp(me), dp(s)))
+    return m, me, s
+
+
+def _dev(t, dtype=torch.float64, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class CoagContext:
+    """coag_create / coag_destroy around one mass grid on the current device."""
+
+    def __init__(self, m, m_edge, s, rho_m=1.67, eta=11.0 / 6.0, chi=1.0, split=L.SPLIT_MASS):
+        self.m = np.ascontiguousarray(m, dtype=np.float64)
+        self.m_edge = np.ascontiguousarray(m_edge, dtype=np.float64)
+        self.s = np.ascontiguousarray(s, dtype=np.float64)
+        self.N = int(self.m.shape[0])
+        self.P = self.N * (self.N + 1) // 2
+        self.rho_m, self.eta, self.chi, self.split = rho_m, eta, chi, split
+        dp = lambda a: a.ctypes.data_as(L._dp)
+        g = L.Grid(self.N, split, dp(self.m), dp(self.m_edge), dp(self.s), rho_m, eta, chi)
+        h = ct.c_void_p()
+        self._lib = L.load()
+        L.check(self._lib.coag_create(ct.byref(g), ct.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.coag_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        L.check(rc, self._h)
+
+    def _cells(self, cells, C):
+        arrs = [_dev(cells[k], shape=(C,), name=k) for k in CELL_KEYS]
+        return L.Cells(*[a.data_ptr() for a in arrs]), arrs
+
+    # ------------------------------------------------------------------ calls
+    def coag_rates(self, cells, v_dust, v_frag, Kc=None, Kf=None):
+        C = int(v_frag.shape[0])
+        cs, keep = self._cells(cells, C)
+        _dev(v_dust, shape=(C, self.N, 3), name="v_dust")
+        _dev(v_frag, shape=(C,), name="v_frag")
+        dev = v_frag.device
+        Kc = torch.empty((C, self.P), dtype=torch.float64, device=dev) if Kc is None else _dev(Kc, shape=(C, self.P), name="Kc")
+        Kf = torch.empty((C, self.P), dtype=torch.float64, device=dev) if Kf is None else _dev(Kf, shape=(C, self.P), name="Kf")
+        self._check(self._lib.coag_rates(self._h, C, ct.byref(cs), _ptr(v_dust), _ptr(v_frag),
+                                         _ptr(Kc), _ptr(Kf), _stream()))
+        return Kc, Kf
+
+    def coag_rhs(self, rho, Kc, Kf, out=None):
+        C = int(rho.shape[0])
+        _dev(rho, shape=(C, self.N), name="rho")
+        _dev(Kc, shape=(C, self.P), name="Kc")
+        _dev(Kf, shape=(C, self.P), name="Kf")
+        out = torch.empty_like(rho) if out is None else _dev(out, shape=(C, self.N), name="out")
+        self._check(self._lib.coag_rhs(self._h, C, _ptr(rho), _ptr(Kc), _ptr(Kf), _ptr(out), _stream()))
+        return out
+
+    def coag_step(self, rho, Kc, Kf, dt, h=None, mode=L.ADAPTIVE, prec=L.PREC_FP64, rtol=1e-2,
+                  atol_rel=1e-10, h_min_rel=1e-12, max_sub=10000, renorm=False, nsub=None,
+                  h_log=None, log=True):
+        """Advances rho (in place) by dt; returns dict(rho, h, nsub, nrej, h_log, status)."""
+        C = int(rho.shape[0])
+        dev = rho.device
+        _dev(rho, shape=(C, self.N), name="rho")
+        _dev(Kc, shape=(C, self.P), name="Kc")
+        _dev(Kf, shape=(C, self.P), name="Kf")
+        if h is None:
+            h = torch.zeros(C, dtype=torch.float64, device=dev)
+        _dev(h, shape=(C,), name="h")
+        if nsub is None:
+            nsub = torch.zeros(C, dtype=torch.int32, device=dev)
+        _dev(nsub, dtype=torch.int32, shape=(C,), name="nsub")
+        if mode == L.REPLAY:
+            if h_log is None:
+                raise ValueError("REPLAY needs h_log")
+            max_sub = int(h_log.shape[1])
+        if h_log is None and log:
+            h_log = torch.zeros((C, max_sub), dtype=torch.float64, device=dev)
+        if h_log is not None:
+            _dev(h_log, shape=(C, max_sub), name="h_log")
+        nrej = torch.zeros(C, dtype=torch.int32, device=dev)
+        status = torch.zeros(C, dtype=torch.int32, device=dev)
+        tol = L.Tol(rtol, atol_rel, h_min_rel, max_sub, mode, prec, 1 if renorm else 0)
+        self._check(self._lib.coag_step(self._h, C, _ptr(rho), _ptr(Kc), _ptr(Kf), float(dt),
+                                        _ptr(h), ct.byref(tol), _ptr(nsub), _ptr(nrej),
+                                        _ptr(h_log), _ptr(status), _stream()))
+        return dict(rho=rho, h=h, nsub=nsub, nrej=nrej, h_log=h_log, status=status)
+
+    def coag_step_backward(self, rho_in, cells, v_dust, v_frag, h_log, nsub, g_out,
+                           prec=L.PREC_FP64):
+        C = int(rho_in.shape[0])
+        _dev(rho_in, shape=(C, self.N), name="rho_in")
+        cs, keep = self._cells(cells, C)
+        _dev(v_dust, shape=(C, self.N, 3), name="v_dust")
+        _dev(v_frag, shape=(C,), name="v_frag")
+        _dev(h_log, name="h_log")
+        _dev(nsub, dtype=torch.int32, shape=(C,), name="nsub")
+        _dev(g_out, shape=(C, self.N), name="g_out")
+        g_in = torch.empty_like(rho_in)
+        g_alpha = torch.empty(C, dtype=torch.float64, device=rho_in.device)
+        g_vfrag = torch.empty(C, dtype=torch.float64, device=rho_in.device)
+        self._check(self._lib.coag_step_backward(self._h, C, _ptr(rho_in), ct.byref(cs),
+                                                 _ptr(v_dust), _ptr(v_frag), _ptr(h_log),
+                                                 int(h_log.shape[1]), _ptr(nsub), _ptr(g_out),
+                                                 _ptr(g_in), _ptr(g_alpha), _ptr(g_vfrag),
+                                                 prec, _stream()))
+        return g_in, g_alpha, g_vfrag
+
+
+def coag_create(m, m_edge, s, **kw) -> CoagContext:
+    return CoagContext(m, m_edge, s, **kw)

@@ -1,0 +1,328 @@
+// coag_api.hip -- the C ABI of libcoag (declared in include/coag.h): argument
+// validation on the host, context lifetime, workspaces and kernel launches.
+// Every numerical step of the path runs in the kernels of coag_kernels.hip and
+// coag_split.hip; this file only checks, allocates and launches.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/coag.h"
+#include "coag_launch.h"
+#include "coag_split.h"
+
+using namespace coag;
+
+struct coag_ctx {
+    int device = -1;
+    int N = 0, P = 0;
+    double rho_m = 0, eta = 0, chi = 0;
+    int split = 0;
+    // device tables
+    void *block = nullptr;                 // one allocation holding every table
+    Tables T{};
+    SplitTables S{};
+    // grow-only workspaces
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::string err;
+};
+
+static thread_local std::string g_err;
+
+static int fail(coag_ctx *ctx, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                               \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(ctx, COAG_EHIP, "%s: %s", #call, hipGetErrorString(e_));         \
+    } while (0)
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+static int ensure_ws(coag_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->ws_bytes) return COAG_OK;
+    if (ctx->ws) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    if (hipMalloc(&ctx->ws, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, COAG_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
+    }
+    ctx->ws_bytes = bytes;
+    return COAG_OK;
+}
+
+static int set_device(coag_ctx *ctx) {
+    int cur = -1;
+    HIP_TRY(ctx, hipGetDevice(&cur));
+    if (cur != ctx->device) HIP_TRY(ctx, hipSetDevice(ctx->device));
+    return COAG_OK;
+}
+
+extern "C" {
+
+int coag_mass_grid(int32_t n_bins, double lo, double hi, int32_t by_mass, double rho_m,
+                   double *m, double *m_edge, double *s) {
+    if (n_bins < 2 || !(lo > 0.0) || !(hi > lo) || !(rho_m > 0.0) || !m || !m_edge || !s)
+        return fail(nullptr, COAG_EINVAL, "coag_mass_grid: need N >= 2, 0 < lo < hi, rho_m > 0 "
+                                          "and non-null outputs");
+    const int N = n_bins;
+    auto mass = [&](double x) { return by_mass ? x : 4.0 * M_PI / 3.0 * rho_m * x * x * x; };
+    for (int k = 0; k <= N; ++k) m_edge[k] = mass(lo * pow(hi / lo, (double)k / (double)N));
+    for (int k = 0; k < N; ++k) {
+        const double x = lo * pow(hi / lo, (k + 0.5) / (double)N);
+        m[k] = mass(x);
+        s[k] = by_mass ? cbrt(3.0 * x / (4.0 * M_PI * rho_m)) : x;
+    }
+    return COAG_OK;
+}
+
+int coag_create(const coag_grid *g, coag_ctx **out) {
+    if (!out) return fail(nullptr, COAG_EINVAL, "coag_create: out is NULL");
+    *out = nullptr;
+    if (!g || !g->m || !g->m_edge || !g->s)
+        return fail(nullptr, COAG_EINVAL, "coag_create: grid or one of its arrays is NULL");
+    const int N = g->n_bins;
+    if (N < 2 || N > kMaxBins)
+        return fail(nullptr, COAG_EINVAL, "coag_create: n_bins = %d outside [2, %d]", N, kMaxBins);
+    for (int k = 0; k < N; ++k) {
+        if (!(g->m[k] > 0.0) || !(g->s[k] > 0.0))
+            return fail(nullptr, COAG_EINVAL, "coag_create: m[%d] or s[%d] not positive", k, k);
+        if (k + 1 < N && !(g->m[k + 1] > g->m[k]))
+            return fail(nullptr, COAG_EINVAL, "coag_create: m not strictly increasing at %d", k);
+        if (!(g->m_edge[k] < g->m[k] && g->m[k] < g->m_edge[k + 1]))
+            return fail(nullptr, COAG_EINVAL, "coag_create: m_edge does not bracket m[%d]", k);
+    }
+    if (!(g->chi > 0.0)) return fail(nullptr, COAG_EINVAL, "coag_create: chi must be > 0");
+    if (!(g->eta == g->eta) || g->eta == 2.0)
+        return fail(nullptr, COAG_EINVAL, "coag_create: eta must be finite and != 2");
+    if (!(g->rho_m > 0.0)) return fail(nullptr, COAG_EINVAL, "coag_create: rho_m must be > 0");
+    if (g->split != COAG_SPLIT_MASS && g->split != COAG_SPLIT_NUMBER)
+        return fail(nullptr, COAG_EINVAL, "coag_create: unknown split %d", g->split);
+
+    coag_ctx *ctx = new coag_ctx();
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, COAG_EHIP, "coag_create: no HIP device");
+    }
+    ctx->N = N;
+    ctx->P = N * (N + 1) / 2;
+    ctx->rho_m = g->rho_m;
+    ctx->eta = g->eta;
+    ctx->chi = g->chi;
+    ctx->split = g->split;
+    const size_t P = ctx->P;
+    // one block: pij, dst (u32 [P]); cw0, cw1, rw0, rw1, fm ([P]); m, s, dE, invE ([N]);
+    // m_edge [N+1]; then the split-precision tables
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    const size_t o_pij = take(4 * P), o_dst = take(4 * P);
+    const size_t o_cw0 = take(8 * P), o_cw1 = take(8 * P), o_rw0 = take(8 * P),
+                 o_rw1 = take(8 * P), o_fm = take(8 * P);
+    const size_t o_m = take(8 * N), o_s = take(8 * N), o_dE = take(8 * N), o_iE = take(8 * N),
+                 o_me = take(8 * (N + 1));
+    const size_t o_split = take(split_tables_bytes(N));
+    if (hipMalloc(&ctx->block, off) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return fail(nullptr, COAG_ENOMEM, "coag_create: table allocation (%zu bytes) failed", off);
+    }
+    char *b = (char *)ctx->block;
+    Tables &T = ctx->T;
+    T.N = N;
+    T.P = (int)P;
+    T.rho_m = g->rho_m;
+    T.pij = (uint32_t *)(b + o_pij);
+    T.dst = (uint32_t *)(b + o_dst);
+    T.cw0 = (double *)(b + o_cw0);
+    T.cw1 = (double *)(b + o_cw1);
+    T.rw0 = (double *)(b + o_rw0);
+    T.rw1 = (double *)(b + o_rw1);
+    T.fm = (double *)(b + o_fm);
+    T.m = (double *)(b + o_m);
+    T.s = (double *)(b + o_s);
+    T.dE = (double *)(b + o_dE);
+    T.invE = (double *)(b + o_iE);
+    double *me = (double *)(b + o_me);
+    int rc = COAG_OK;
+    hipError_t e = hipMemcpy((void *)T.m, g->m, 8 * N, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void *)T.s, g->s, 8 * N, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(me, g->m_edge, 8 * (N + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_build(N, T.m, me, g->eta, g->chi, g->split, (uint32_t *)T.pij,
+                         (uint32_t *)T.dst, (double *)T.cw0, (double *)T.cw1, (double *)T.rw0,
+                         (double *)T.rw1, (double *)T.fm, (double *)T.dE, (double *)T.invE,
+                         nullptr);
+    if (e == hipSuccess) e = build_split_tables(T, b + o_split, &ctx->S, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = fail(nullptr, COAG_EHIP, "coag_create: %s", hipGetErrorString(e));
+    if (rc != COAG_OK) {
+        (void)hipFree(ctx->block);
+        delete ctx;
+        return rc;
+    }
+    *out = ctx;
+    return COAG_OK;
+}
+
+void coag_destroy(coag_ctx *ctx) {
+    if (!ctx) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->block) (void)hipFree(ctx->block);
+    if (cur >= 0) (void)hipSetDevice(cur);
+    delete ctx;
+}
+
+const char *coag_last_error(const coag_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+static int check_cells(coag_ctx *ctx, const coag_cells *c) {
+    if (!c || !c->T || !c->rho_g || !c->c_s || !c->Omega || !c->H || !c->nu_mol || !c->alpha)
+        return fail(ctx, COAG_EINVAL, "cells or one of its arrays is NULL");
+    return COAG_OK;
+}
+
+static CellArrays cell_arrays(const coag_cells *c) {
+    return CellArrays{c->T, c->rho_g, c->c_s, c->Omega, c->H, c->nu_mol, c->alpha};
+}
+
+int coag_rates(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
+               const double *v_frag, double *Kc, double *Kf, void *stream) {
+    if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_rates: ctx is NULL");
+    if (C < 0 || C > 0x7fffffff) return fail(ctx, COAG_EINVAL, "coag_rates: bad C = %lld", (long long)C);
+    if (int r = check_cells(ctx, cells)) return r;
+    if (!v_dust || !v_frag || !Kc || !Kf) return fail(ctx, COAG_EINVAL, "coag_rates: NULL array");
+    if (int r = set_device(ctx)) return r;
+    HIP_TRY(ctx, launch_rates(ctx->T, C, cell_arrays(cells), v_dust, v_frag, Kc, Kf,
+                              (hipStream_t)stream));
+    return COAG_OK;
+}
+
+int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, const double *Kf,
+             double *drho_dt, void *stream) {
+    if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_rhs: ctx is NULL");
+    if (C < 0 || C > 0x7fffffff) return fail(ctx, COAG_EINVAL, "coag_rhs: bad C = %lld", (long long)C);
+    if (!rho || !Kc || !Kf || !drho_dt) return fail(ctx, COAG_EINVAL, "coag_rhs: NULL array");
+    if (int r = set_device(ctx)) return r;
+    HIP_TRY(ctx, launch_rhs(ctx->T, C, rho, Kc, Kf, drho_dt, (hipStream_t)stream));
+    return COAG_OK;
+}
+
+int coag_step(coag_ctx *ctx, int64_t C, double *rho, const double *Kc, const double *Kf,
+              double dt, double *h, const coag_tol *tol, int32_t *nsub, int32_t *nrej,
+              double *h_log, int32_t *status, void *stream) {
+    if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_step: ctx is NULL");
+    if (C < 0 || C > 0x7fffffff) return fail(ctx, COAG_EINVAL, "coag_step: bad C = %lld", (long long)C);
+    if (!tol) return fail(ctx, COAG_EINVAL, "coag_step: tol is NULL");
+    if (!rho || !Kc || !Kf || !nsub || !status)
+        return fail(ctx, COAG_EINVAL, "coag_step: rho, Kc, Kf, nsub and status are required");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(ctx, COAG_EINVAL, "coag_step: dt must be > 0");
+    if (tol->mode < COAG_ADAPTIVE || tol->mode > COAG_REPLAY)
+        return fail(ctx, COAG_EINVAL, "coag_step: unknown mode %d", tol->mode);
+    if (tol->prec != COAG_PREC_FP64 && tol->prec != COAG_PREC_SPLIT_BF16)
+        return fail(ctx, COAG_EINVAL, "coag_step: unknown precision %d", tol->prec);
+    if (tol->max_sub < 1) return fail(ctx, COAG_EINVAL, "coag_step: max_sub must be >= 1");
+    if (tol->mode == COAG_ADAPTIVE) {
+        if (!h) return fail(ctx, COAG_EINVAL, "coag_step: h is required in ADAPTIVE mode");
+        if (!(tol->rtol > 0.0) || !(tol->atol_rel >= 0.0) || !(tol->h_min_rel >= 0.0))
+            return fail(ctx, COAG_EINVAL, "coag_step: need rtol > 0, atol_rel >= 0, h_min_rel >= 0");
+    }
+    if (tol->mode == COAG_REPLAY && !h_log)
+        return fail(ctx, COAG_EINVAL, "coag_step: h_log is required in REPLAY mode");
+    if (int r = set_device(ctx)) return r;
+    StepArgs a;
+    a.rho = rho;
+    a.Kc = Kc;
+    a.Kf = Kf;
+    a.dt = dt;
+    a.h = h;
+    a.rtol = tol->rtol;
+    a.atol_rel = tol->atol_rel;
+    a.h_min_rel = tol->h_min_rel;
+    a.max_sub = tol->max_sub;
+    a.mode = tol->mode;
+    a.renorm = tol->renorm;
+    a.nsub = nsub;
+    a.nrej = nrej;
+    a.status = status;
+    a.h_log = h_log;
+    if (tol->prec == COAG_PREC_SPLIT_BF16) {
+        const size_t need = split_step_ws_bytes(ctx->N, C);
+        if (int r = ensure_ws(ctx, need)) return r;
+        HIP_TRY(ctx, launch_step_split(ctx->T, ctx->S, C, a, ctx->ws, (hipStream_t)stream));
+    } else {
+        HIP_TRY(ctx, launch_step(ctx->T, C, a, (hipStream_t)stream));
+    }
+    return COAG_OK;
+}
+
+int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coag_cells *cells,
+                       const double *v_dust, const double *v_frag, const double *h_log,
+                       int32_t log_stride, const int32_t *nsub, const double *g_out,
+                       double *g_in, double *g_alpha, double *g_vfrag, int32_t prec,
+                       void *stream) {
+    if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_step_backward: ctx is NULL");
+    if (C < 0 || C > 0x7fffffff)
+        return fail(ctx, COAG_EINVAL, "coag_step_backward: bad C = %lld", (long long)C);
+    if (int r = check_cells(ctx, cells)) return r;
+    if (!rho_in || !v_dust || !v_frag || !h_log || !nsub || !g_out || !g_in || !g_alpha || !g_vfrag)
+        return fail(ctx, COAG_EINVAL, "coag_step_backward: NULL array");
+    if (log_stride < 1) return fail(ctx, COAG_EINVAL, "coag_step_backward: log_stride must be >= 1");
+    if (prec != COAG_PREC_FP64 && prec != COAG_PREC_SPLIT_BF16)
+        return fail(ctx, COAG_EINVAL, "coag_step_backward: unknown precision %d", prec);
+    if (int r = set_device(ctx)) return r;
+    const size_t P = ctx->P, N = ctx->N;
+    const size_t bK = align256(8 * P * (size_t)C);
+    const size_t bY = align256(8 * N * (size_t)(log_stride + 1) * (size_t)C);
+    const size_t split_extra = prec == COAG_PREC_SPLIT_BF16 ? split_adjoint_ws_bytes(ctx->N, C) : 0;
+    if (int r = ensure_ws(ctx, 4 * bK + bY + split_extra)) return r;
+    char *w = (char *)ctx->ws;
+    double *Kc = (double *)w, *Kf = (double *)(w + bK), *gKc = (double *)(w + 2 * bK),
+           *gKf = (double *)(w + 3 * bK), *Ys = (double *)(w + 4 * bK);
+    const CellArrays ca = cell_arrays(cells);
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(ctx, launch_rates(ctx->T, C, ca, v_dust, v_frag, Kc, Kf, st));
+    AdjArgs a;
+    a.rho_in = rho_in;
+    a.Kc = Kc;
+    a.Kf = Kf;
+    a.gKc = gKc;
+    a.gKf = gKf;
+    a.Ys = Ys;
+    a.h_log = h_log;
+    a.log_stride = log_stride;
+    a.nsub = nsub;
+    a.g_out = g_out;
+    a.g_in = g_in;
+    if (prec == COAG_PREC_SPLIT_BF16) {
+        HIP_TRY(ctx, launch_adjoint_split(ctx->T, ctx->S, C, a, ca, v_dust, v_frag, g_alpha,
+                                          g_vfrag, w + 4 * bK + bY, st));
+    } else {
+        HIP_TRY(ctx, launch_adjoint(ctx->T, C, a, ca, v_dust, v_frag, g_alpha, g_vfrag, st));
+    }
+    return COAG_OK;
+}
+
+}  // extern "C"
