@@ -66,7 +66,7 @@ int oracle_mass_grid(int N, double lo, double hi, int by_mass, double rho_m,
 
 /* Two-bin split of a product of mass M (eqs. `Cijk`, `Rijk`).
    l(M) = largest k with m_k <= M (an exact hit goes wholly to that bin),
-   u = l + 1, eps = (m_u - M) / (m_u - m_l).
+   u = l + 1, eps = (m_u - M) / (m_u - m_l), 1 - eps = (M - m_l) / (m_u - m_l).
    MASS  : mass eps*M to l and (1-eps)*M to u   (C_ijk as a mass fraction)
    NUMBER: mass eps*m_l to l and (1-eps)*m_u to u (one particle split by number)
    Products at or above the top bin go wholly to N-1, below bin 0 wholly to 0. */
@@ -81,14 +81,17 @@ static void split_mass(const double *m, int N, double M, int split,
     for (int q = 0; q < N; ++q)
         if (m[q] <= M) l = q;
     int u = l + 1;
+    /* eps and 1 - eps, the latter written as (M - m_l)/(m_u - m_l) so that it
+       does not cancel when M is close to m_l on a coarse grid */
     double eps = (m[u] - M) / (m[u] - m[l]);
+    double ome = (M - m[l]) / (m[u] - m[l]);
     *k = l;
     if (split == ORACLE_SPLIT_NUMBER) {
         *w0 = eps * m[l];
-        *w1 = (1.0 - eps) * m[u];
+        *w1 = ome * m[u];
     } else {
         *w0 = eps * M;
-        *w1 = (1.0 - eps) * M;
+        *w1 = ome * M;
     }
 }
 

@@ -33,14 +33,16 @@ __device__ void split_mass(const double *m, int N, double M, int split, int *k, 
         const int mid = (lo + hi) >> 1;
         if (m[mid] <= M) lo = mid; else hi = mid;
     }
-    const double eps = (m[lo + 1] - M) / (m[lo + 1] - m[lo]);
+    // eps and 1 - eps; the latter as (M - m_l) / (m_u - m_l), free of cancellation
+    const double den = m[lo + 1] - m[lo];
+    const double eps = (m[lo + 1] - M) / den, ome = (M - m[lo]) / den;
     *k = lo;
     if (split == 1) {                      // NUMBER: one particle split by number
         *w0 = eps * m[lo];
-        *w1 = (1.0 - eps) * m[lo + 1];
+        *w1 = ome * m[lo + 1];
     } else {                               // MASS: mass fractions eps, 1 - eps
         *w0 = eps * M;
-        *w1 = (1.0 - eps) * M;
+        *w1 = ome * M;
     }
 }
 

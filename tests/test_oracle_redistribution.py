@@ -143,3 +143,17 @@ def test_bad_grid_rejected(O):
     g = O.make_grid(8, 1e-5, 1.0, eta=2.0)
     with pytest.raises(ValueError):
         O.redistribution_dense(g)
+
+
+@pytest.mark.parametrize("split", [0, 1])
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_rows_conserve_mass_on_coarse_grids(O, split, n):
+    """Very coarse grids (up to 18 decades of mass per bin): the split must
+    still deposit exactly m_i + m_j (1 - eps is evaluated without the
+    cancellation of 1 - (m_u - M)/(m_u - m_l))."""
+    for chi in (0.5, 1.0, 2.0):
+        g = O.make_grid(n, 1e-5, 10.0, chi=chi, split=split)
+        D = O.redistribution_dense(g)
+        tot = np.array([g.m[i] + g.m[j] for i, j in _pairs(g.N)])
+        np.testing.assert_allclose(D[: g.P].sum(1), tot, rtol=1e-15)
+        np.testing.assert_allclose(D[g.P:].sum(1), tot, rtol=1e-15)
