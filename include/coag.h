@@ -26,6 +26,7 @@
  *     the host before anything is launched (nothing is written then); the
  *     message is in coag_last_error().  Failures inside a cell are reported in
  *     that cell's `status` and never stop other cells.
+ *   - C = 0 is a valid no-op; array pointers may then be NULL.
  *   - A context is bound to one device and is not thread-safe; calls that
  *     overlap on the same context must not share the context's workspace
  *     (use one context per stream).

@@ -1,0 +1,82 @@
+"""torch.autograd.Function around repeated coagulation calls, with the
+hand-written adjoint of libcoag (coag_step_backward) as its backward.
+
+Forward: n_steps calls of coag_rates + coag_step (ADAPTIVE), recording each
+call's accepted step sizes and keeping the state every `ckpt_every` calls.
+Backward: for each checkpoint segment, from the last to the first, the
+segment is recomputed from its checkpoint with the recorded step sizes
+(REPLAY, so the step sequence is exactly the one the forward pass took) and
+the adjoint runs through its calls in reverse.  Gradients are returned for the
+initial density, alpha and v_frag (per cell); the other inputs are not
+differentiated.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+
+class CoagStep(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rho0, alpha, v_frag, coag, cells, v_dust, dt, n_steps, ckpt_every=20,
+                prec=L.PREC_FP64, max_sub=64, rtol=1e-2, atol_rel=1e-10):
+        C = rho0.shape[0]
+        dev = rho0.device
+        cells = dict(cells)
+        cells["alpha"] = alpha.detach().contiguous()
+        vf = v_frag.detach().contiguous()
+        rho = rho0.detach().clone()
+        h = torch.zeros(C, dtype=torch.float64, device=dev)
+        logs = torch.zeros((n_steps, C, max_sub), dtype=torch.float64, device=dev)
+        nsubs = torch.zeros((n_steps, C), dtype=torch.int32, device=dev)
+        ckpts = []
+        for s in range(n_steps):
+            if s % ckpt_every == 0:
+                ckpts.append(rho.clone())
+            Kc, Kf = coag.coag_rates(cells, v_dust, vf)
+            r = coag.coag_step(rho, Kc, Kf, dt, h=h, mode=L.ADAPTIVE, prec=prec, rtol=rtol,
+                               atol_rel=atol_rel, max_sub=max_sub, nsub=nsubs[s], h_log=logs[s])
+            st = r["status"]
+            if bool((st != 0).any()):
+                bad = int((st != 0).sum())
+                raise RuntimeError(f"coag_step: {bad} cells failed at call {s} "
+                                   f"(status codes {sorted(set(st.tolist()))})")
+        ctx.coag, ctx.cells, ctx.v_dust, ctx.vf = coag, cells, v_dust, vf
+        ctx.dt, ctx.n_steps, ctx.ckpt_every, ctx.prec = dt, n_steps, ckpt_every, prec
+        ctx.logs, ctx.nsubs, ctx.ckpts = logs, nsubs, ckpts
+        return rho
+
+    @staticmethod
+    def backward(ctx, g_out):
+        coag, cells, v_dust, vf = ctx.coag, ctx.cells, ctx.v_dust, ctx.vf
+        g = g_out.detach().contiguous().clone()
+        C = g.shape[0]
+        g_alpha = torch.zeros(C, dtype=torch.float64, device=g.device)
+        g_vfrag = torch.zeros_like(g_alpha)
+        n, E = ctx.n_steps, ctx.ckpt_every
+        for seg in range((n + E - 1) // E - 1, -1, -1):
+            s0, s1 = seg * E, min((seg + 1) * E, n)
+            # recompute the segment from its checkpoint, keeping each call's start state
+            rho = ctx.ckpts[seg].clone()
+            starts = []
+            for s in range(s0, s1):
+                starts.append(rho.clone())
+                if s + 1 < s1:
+                    Kc, Kf = coag.coag_rates(cells, v_dust, vf)
+                    coag.coag_step(rho, Kc, Kf, ctx.dt, mode=L.REPLAY, prec=ctx.prec,
+                                   nsub=ctx.nsubs[s], h_log=ctx.logs[s])
+            for s in range(s1 - 1, s0 - 1, -1):
+                gi, ga, gv = coag.coag_step_backward(starts[s - s0], cells, v_dust, vf,
+                                                     ctx.logs[s], ctx.nsubs[s], g, prec=ctx.prec)
+                g = gi
+                g_alpha += ga
+                g_vfrag += gv
+        return (g, g_alpha, g_vfrag) + (None,) * 10
+
+
+def coag_evolve(coag, rho0, alpha, v_frag, cells, v_dust, dt, n_steps, ckpt_every=20,
+                prec=L.PREC_FP64, max_sub=64):
+    """Differentiable n_steps coagulation calls (see CoagStep)."""
+    return CoagStep.apply(rho0, alpha, v_frag, coag, cells, v_dust, dt, n_steps, ckpt_every,
+                          prec, max_sub)

@@ -212,6 +212,7 @@ int coag_rates(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *
                const double *v_frag, double *Kc, double *Kf, void *stream) {
     if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_rates: ctx is NULL");
     if (C < 0 || C > 0x7fffffff) return fail(ctx, COAG_EINVAL, "coag_rates: bad C = %lld", (long long)C);
+    if (C == 0) return COAG_OK;                 // nothing to read or write
     if (int r = check_cells(ctx, cells)) return r;
     if (!v_dust || !v_frag || !Kc || !Kf) return fail(ctx, COAG_EINVAL, "coag_rates: NULL array");
     if (int r = set_device(ctx)) return r;
@@ -224,6 +225,7 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
              double *drho_dt, void *stream) {
     if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_rhs: ctx is NULL");
     if (C < 0 || C > 0x7fffffff) return fail(ctx, COAG_EINVAL, "coag_rhs: bad C = %lld", (long long)C);
+    if (C == 0) return COAG_OK;
     if (!rho || !Kc || !Kf || !drho_dt) return fail(ctx, COAG_EINVAL, "coag_rhs: NULL array");
     if (int r = set_device(ctx)) return r;
     HIP_TRY(ctx, launch_rhs(ctx->T, C, rho, Kc, Kf, drho_dt, (hipStream_t)stream));
@@ -236,7 +238,7 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const double *Kc, const dou
     if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_step: ctx is NULL");
     if (C < 0 || C > 0x7fffffff) return fail(ctx, COAG_EINVAL, "coag_step: bad C = %lld", (long long)C);
     if (!tol) return fail(ctx, COAG_EINVAL, "coag_step: tol is NULL");
-    if (!rho || !Kc || !Kf || !nsub || !status)
+    if (C > 0 && (!rho || !Kc || !Kf || !nsub || !status))
         return fail(ctx, COAG_EINVAL, "coag_step: rho, Kc, Kf, nsub and status are required");
     if (!(dt > 0.0) || !isfinite(dt)) return fail(ctx, COAG_EINVAL, "coag_step: dt must be > 0");
     if (tol->mode < COAG_ADAPTIVE || tol->mode > COAG_REPLAY)
@@ -245,12 +247,13 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const double *Kc, const dou
         return fail(ctx, COAG_EINVAL, "coag_step: unknown precision %d", tol->prec);
     if (tol->max_sub < 1) return fail(ctx, COAG_EINVAL, "coag_step: max_sub must be >= 1");
     if (tol->mode == COAG_ADAPTIVE) {
-        if (!h) return fail(ctx, COAG_EINVAL, "coag_step: h is required in ADAPTIVE mode");
+        if (!h && C > 0) return fail(ctx, COAG_EINVAL, "coag_step: h is required in ADAPTIVE mode");
         if (!(tol->rtol > 0.0) || !(tol->atol_rel >= 0.0) || !(tol->h_min_rel >= 0.0))
             return fail(ctx, COAG_EINVAL, "coag_step: need rtol > 0, atol_rel >= 0, h_min_rel >= 0");
     }
-    if (tol->mode == COAG_REPLAY && !h_log)
+    if (tol->mode == COAG_REPLAY && !h_log && C > 0)
         return fail(ctx, COAG_EINVAL, "coag_step: h_log is required in REPLAY mode");
+    if (C == 0) return COAG_OK;
     if (int r = set_device(ctx)) return r;
     StepArgs a;
     a.rho = rho;
@@ -286,6 +289,10 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
     if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_step_backward: ctx is NULL");
     if (C < 0 || C > 0x7fffffff)
         return fail(ctx, COAG_EINVAL, "coag_step_backward: bad C = %lld", (long long)C);
+    if (prec != COAG_PREC_FP64 && prec != COAG_PREC_SPLIT_BF16)
+        return fail(ctx, COAG_EINVAL, "coag_step_backward: unknown precision %d", prec);
+    if (log_stride < 1) return fail(ctx, COAG_EINVAL, "coag_step_backward: log_stride must be >= 1");
+    if (C == 0) return COAG_OK;
     if (int r = check_cells(ctx, cells)) return r;
     if (!rho_in || !v_dust || !v_frag || !h_log || !nsub || !g_out || !g_in || !g_alpha || !g_vfrag)
         return fail(ctx, COAG_EINVAL, "coag_step_backward: NULL array");
