@@ -53,7 +53,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(cfg, disc_mod, n_cells, target_s=10.0, max_calls=200):
+def cpu_baseline(cfg, disc_mod, n_cells, target_s=10.0, max_calls=2000):
     """The oracle, untouched, on a bounded sample of the same workload:
     n_cells cells spread evenly over the disc, repeated coagulation calls
     (rates + adaptive step over dt, state carried) until about target_s of

@@ -137,7 +137,8 @@ int coag_create(const coag_grid *g, coag_ctx **out) {
     const size_t o_cw0 = take(8 * P), o_cw1 = take(8 * P), o_rw0 = take(8 * P),
                  o_rw1 = take(8 * P), o_fm = take(8 * P);
     const size_t o_m = take(8 * N), o_s = take(8 * N), o_dE = take(8 * N), o_iE = take(8 * N),
-                 o_me = take(8 * (N + 1));
+                 o_me = take(8 * (N + 1)), o_idm = take(8 * N), o_fc = take(4 * N),
+                 o_fr = take(4 * N);
     const size_t o_split = take(split_tables_bytes(N));
     if (hipMalloc(&ctx->block, off) != hipSuccess) {
         (void)hipGetLastError();
@@ -160,6 +161,11 @@ int coag_create(const coag_grid *g, coag_ctx **out) {
     T.s = (double *)(b + o_s);
     T.dE = (double *)(b + o_dE);
     T.invE = (double *)(b + o_iE);
+    T.invdm = (double *)(b + o_idm);
+    T.fcol = (int *)(b + o_fc);
+    T.frow = (int *)(b + o_fr);
+    T.chi = g->chi;
+    T.split = g->split;
     double *me = (double *)(b + o_me);
     int rc = COAG_OK;
     hipError_t e = hipMemcpy((void *)T.m, g->m, 8 * N, hipMemcpyHostToDevice);
@@ -169,7 +175,7 @@ int coag_create(const coag_grid *g, coag_ctx **out) {
         e = launch_build(N, T.m, me, g->eta, g->chi, g->split, (uint32_t *)T.pij,
                          (uint32_t *)T.dst, (double *)T.cw0, (double *)T.cw1, (double *)T.rw0,
                          (double *)T.rw1, (double *)T.fm, (double *)T.dE, (double *)T.invE,
-                         nullptr);
+                         (double *)T.invdm, (int *)T.fcol, (int *)T.frow, nullptr);
     if (e == hipSuccess) e = build_split_tables(T, b + o_split, &ctx->S, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) rc = fail(nullptr, COAG_EHIP, "coag_create: %s", hipGetErrorString(e));
@@ -228,7 +234,10 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
     if (C == 0) return COAG_OK;
     if (!rho || !Kc || !Kf || !drho_dt) return fail(ctx, COAG_EINVAL, "coag_rhs: NULL array");
     if (int r = set_device(ctx)) return r;
-    HIP_TRY(ctx, launch_rhs(ctx->T, C, rho, Kc, Kf, drho_dt, (hipStream_t)stream));
+    if (reg_path_available(ctx->N))
+        HIP_TRY(ctx, launch_rhs2(ctx->T, C, rho, Kc, Kf, drho_dt, (hipStream_t)stream));
+    else
+        HIP_TRY(ctx, launch_rhs(ctx->T, C, rho, Kc, Kf, drho_dt, (hipStream_t)stream));
     return COAG_OK;
 }
 
@@ -275,6 +284,8 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const double *Kc, const dou
         const size_t need = split_step_ws_bytes(ctx->N, C);
         if (int r = ensure_ws(ctx, need)) return r;
         HIP_TRY(ctx, launch_step_split(ctx->T, ctx->S, C, a, ctx->ws, (hipStream_t)stream));
+    } else if (reg_path_available(ctx->N)) {
+        HIP_TRY(ctx, launch_step2(ctx->T, C, a, (hipStream_t)stream));
     } else {
         HIP_TRY(ctx, launch_step(ctx->T, C, a, (hipStream_t)stream));
     }

@@ -30,6 +30,12 @@ struct Tables {
     const double *s;       // [N] grain radii
     const double *dE;      // [N] E_{k+1} - E_k,   E_k = (m^e_k)^(2 - eta)
     const double *invE;    // [N] 1 / (E_{l+1} - E_0)
+    // per-bin tables of the register-resident kernels
+    const double *invdm;   // [N] 1 / (m_{k+1} - m_k)  (0 for the top bin)
+    const int *fcol;       // [N] top fragment bin when the largest fragment is chi m_j
+    const int *frow;       // [N] top fragment bin when the largest fragment is m_i
+    double chi;            // excavated mass / impactor mass
+    int split;             // 0 MASS, 1 NUMBER
 };
 
 __device__ __forceinline__ int pair_i(uint32_t v) { return v & 1023u; }

@@ -19,6 +19,8 @@ namespace coag {
 // exact hit goes wholly to its bin); products at or above the top bin go to
 // N-1, remnants below bin 0 go to bin 0.
 // ---------------------------------------------------------------------------
+__device__ int top_fragment_bin(const double *me, int N, double x);
+
 __device__ void split_mass(const double *m, int N, double M, int split, int *k, double *w0,
                            double *w1) {
 #pragma clang fp contract(off)
@@ -70,12 +72,7 @@ __global__ void k_build_pairs(int N, const double *__restrict__ m, const double 
         mfmax = m[i];
     }
     split_mass(m, N, mrem, split, &r, &b0, &b1);
-    int lo = 0, hi = N;                    // smallest l with me[l+1] > mfmax
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (me[mid + 1] > mfmax) hi = mid; else lo = mid + 1;
-    }
-    const int f = lo < N ? lo : N - 1;
+    const int f = top_fragment_bin(me, N, mfmax);
     pij[p] = (uint32_t)i | ((uint32_t)j << 10);
     dst[p] = (uint32_t)c | ((uint32_t)r << 10) | ((uint32_t)f << 20);
     cw0[p] = a0;
@@ -85,15 +82,32 @@ __global__ void k_build_pairs(int N, const double *__restrict__ m, const double 
     fm[p] = (m[i] + m[j]) - mrem;
 }
 
-// E_k = (m^e_k)^(2 - eta);  dE_k = E_{k+1} - E_k;  invE_l = 1 / (E_{l+1} - E_0)
-__global__ void k_build_frag(int N, const double *__restrict__ me, double eta, double *dE,
-                             double *invE) {
+// smallest l with me[l+1] > x, clipped to N-1
+__device__ int top_fragment_bin(const double *me, int N, double x) {
+    int lo = 0, hi = N;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (me[mid + 1] > x) hi = mid; else lo = mid + 1;
+    }
+    return lo < N ? lo : N - 1;
+}
+
+// Per-bin tables: E_k = (m^e_k)^(2 - eta);  dE_k = E_{k+1} - E_k;
+// invE_l = 1 / (E_{l+1} - E_0); 1 / (m_{k+1} - m_k); top fragment bins for a
+// largest fragment of chi m_k (cratering) and of m_k (target destroyed).
+__global__ void k_build_frag(int N, const double *__restrict__ m, const double *__restrict__ me,
+                             double eta, double chi, double *dE, double *invE, double *invdm,
+                             int *fcol, int *frow) {
+#pragma clang fp contract(off)
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const double e0 = pow(me[0], 2.0 - eta);
     const double ek = pow(me[k], 2.0 - eta), ek1 = pow(me[k + 1], 2.0 - eta);
     dE[k] = ek1 - ek;
     invE[k] = 1.0 / (ek1 - e0);
+    invdm[k] = k + 1 < N ? 1.0 / (m[k + 1] - m[k]) : 0.0;
+    fcol[k] = top_fragment_bin(me, N, chi * m[k]);
+    frow[k] = top_fragment_bin(me, N, m[k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -461,11 +475,12 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 hipError_t launch_build(int N, const double *m, const double *me, double eta, double chi,
                         int split, uint32_t *pij, uint32_t *dst, double *cw0, double *cw1,
                         double *rw0, double *rw1, double *fm, double *dE, double *invE,
-                        hipStream_t st) {
+                        double *invdm, int *fcol, int *frow, hipStream_t st) {
     const int P = N * (N + 1) / 2;
     hipLaunchKernelGGL(k_build_pairs, dim3((P + 255) / 256), dim3(256), 0, st, N, m, me, chi,
                        split, pij, dst, cw0, cw1, rw0, rw1, fm);
-    hipLaunchKernelGGL(k_build_frag, dim3((N + 255) / 256), dim3(256), 0, st, N, me, eta, dE, invE);
+    hipLaunchKernelGGL(k_build_frag, dim3((N + 255) / 256), dim3(256), 0, st, N, m, me, eta, chi,
+                       dE, invE, invdm, fcol, frow);
     return hipGetLastError();
 }
 

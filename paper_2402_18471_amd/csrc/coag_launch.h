@@ -39,13 +39,19 @@ struct AdjArgs {
 hipError_t launch_build(int N, const double *m, const double *me, double eta, double chi,
                         int split, uint32_t *pij, uint32_t *dst, double *cw0, double *cw1,
                         double *rw0, double *rw1, double *fm, double *dE, double *invE,
-                        hipStream_t st);
+                        double *invdm, int *fcol, int *frow, hipStream_t st);
 hipError_t launch_rates(const Tables &T, long C, const CellArrays &cells, const double *v_dust,
                         const double *v_frag, double *Kc, double *Kf, hipStream_t st);
 hipError_t launch_rhs(const Tables &T, long C, const double *rho, const double *Kc,
                       const double *Kf, double *out, hipStream_t st);
 size_t step_lds_bytes(int N);
 hipError_t launch_step(const Tables &T, long C, const StepArgs &a, hipStream_t st);
+// register-resident FP64 path (coag_step2.hip), for bin counts whose pair
+// triangle fits the registers of one workgroup
+bool reg_path_available(int N);
+hipError_t launch_rhs2(const Tables &T, long C, const double *rho, const double *Kc,
+                       const double *Kf, double *out, hipStream_t st);
+hipError_t launch_step2(const Tables &T, long C, const StepArgs &a, hipStream_t st);
 hipError_t launch_adjoint(const Tables &T, long C, const AdjArgs &a, const CellArrays &cells,
                           const double *v_dust, const double *v_frag, double *g_alpha,
                           double *g_vfrag, hipStream_t st);
