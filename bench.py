@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--config", default="disc256x128_n150")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-cells", type=int, default=512)
+    ap.add_argument("--prec", choices=("fp64", "split"), default="fp64")
+    ap.add_argument("--rates", choices=("f64", "f32"), default="f64")
+    ap.add_argument("--kernel", choices=("batch", "cell"), default="batch")
     return ap.parse_args()
 
 
@@ -91,6 +94,12 @@ def main():
 
     cfg = disc.CONFIGS[args.config]
     dev = "cuda:0"
+    if args.kernel == "cell":
+        os.environ["COAG_STEP_KERNEL"] = "cell"
+    split = args.prec == "split"
+    f32 = args.rates == "f32"
+    if f32 and not split:
+        sys.exit("--rates f32 needs --prec split")
     m, me, s = coag_mass_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
     d = disc.make_disc(cfg, s)
     C, N = cfg.n_cells, cfg.n_bins
@@ -104,12 +113,14 @@ def main():
     nsub_all = torch.zeros((args.warmup + K, C), dtype=torch.int32, device=dev)
     nrej_all = torch.zeros((args.warmup + K, C), dtype=torch.int32, device=dev)
     status = torch.zeros(C, dtype=torch.int32, device=dev)
-    Kc = torch.empty((C, ctx.P), dtype=torch.float64, device=dev)
+    Kc = torch.empty((C, ctx.P), dtype=torch.float32 if f32 else torch.float64, device=dev)
     Kf = torch.empty_like(Kc)
     from paper_2402_18471_amd import _lib as L
     import ctypes as ct
     lib = L.load()
-    tol = L.Tol(1e-2, 1e-10, 1e-12, 4096, L.ADAPTIVE, L.PREC_FP64, 0)
+    tol = L.Tol(1e-2, 1e-10, 1e-12, 4096, L.ADAPTIVE,
+                L.PREC_SPLIT_BF16 if split else L.PREC_FP64, 0, 1 if f32 else 0)
+    rates_fn = lib.coag_rates_f32 if f32 else lib.coag_rates
     cs = L.Cells(*[cells[k].data_ptr() for k in ("T", "rho_g", "c_s", "Omega", "H", "nu_mol", "alpha")])
     stream = torch.cuda.current_stream()
     sp = ct.c_void_p(stream.cuda_stream)
@@ -120,7 +131,7 @@ def main():
     def one(i):
         e0, e1, e2 = ev[i]
         e0.record(stream)
-        L.check(lib.coag_rates(ctx._h, C, ct.byref(cs), p(v_dust), p(v_frag), p(Kc), p(Kf), sp), ctx._h)
+        L.check(rates_fn(ctx._h, C, ct.byref(cs), p(v_dust), p(v_frag), p(Kc), p(Kf), sp), ctx._h)
         e1.record(stream)
         L.check(lib.coag_step(ctx._h, C, p(rho), p(Kc), p(Kf), float(d["dt"]), p(h), ct.byref(tol),
                               p(nsub_all[i]), p(nrej_all[i]), None, p(status), sp), ctx._h)

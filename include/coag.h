@@ -99,10 +99,12 @@ typedef struct {
    mode: COAG_ADAPTIVE / COAG_FIXED / COAG_REPLAY.  max_sub: cap on attempted
    sub-steps per cell per call (ADAPTIVE), and the row length of h_log.
    prec: COAG_PREC_*.  renorm: non-zero rescales each cell's state after the
-   call so that its total mass equals the total at entry. */
+   call so that its total mass equals the total at entry (COAG_PREC_SPLIT_BF16
+   always does).  rates_f32: 1 if the Kc, Kf handed to coag_step are float
+   arrays from coag_rates_f32 (COAG_PREC_SPLIT_BF16 only), 0 for double. */
 typedef struct {
     double rtol, atol_rel, h_min_rel;
-    int32_t max_sub, mode, prec, renorm;
+    int32_t max_sub, mode, prec, renorm, rates_f32;
 } coag_tol;
 
 /* ------------------------------------------------------------------------- */
@@ -145,6 +147,12 @@ const char *coag_last_error(const coag_ctx *ctx);
 int coag_rates(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
                const double *v_frag, double *Kc, double *Kf, void *stream);
 
+/* The same rates rounded to FP32 (Kc, Kf float [C][P] DEVICE out), for the
+   split-BF16 step (coag_tol.rates_f32 = 1), which then streams half the bytes
+   per right-hand side.  Errors as coag_rates. */
+int coag_rates_f32(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
+                   const double *v_frag, float *Kc, float *Kf, void *stream);
+
 /* Right-hand side of eq. `smol` for C cells:
      drho_k = sum_{i, j<=i} n_i n_j [Kc (m_i+m_j) C_ijk + Kf (m_rem R_ijk + m_frag F_ijk)]
               - m_k n_k sum_i K_ik n_i (p_c + p_f),      n = rho / m,
@@ -166,7 +174,8 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
    a clipped accepted step leaves h unchanged.  FIXED: nsub[c] equal steps of
    dt/nsub[c].  REPLAY: nsub[c] steps of the sizes h_log[c][0..nsub[c]).
      rho     [C][N]        DEVICE in/out
-     Kc, Kf  [C][P]        DEVICE in (from coag_rates, or any kernel)
+     Kc, Kf  [C][P]        DEVICE in (from coag_rates, or any kernel): double, or
+                           float when tol->rates_f32 = 1
      h       [C]           DEVICE in/out (ADAPTIVE): h <= 0 on entry starts with dt;
                            on exit the controller's next (unclipped) step size
      nsub    [C] int32     DEVICE out (ADAPTIVE: accepted steps) or in (FIXED, REPLAY)
@@ -174,9 +183,21 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
      h_log   [C][max_sub]  DEVICE out (ADAPTIVE, FIXED: accepted step sizes; may be
                            NULL) or in (REPLAY, required)
      status  [C] int32     DEVICE out, COAG_CELL_*
+   Arithmetic (tol->prec):
+     COAG_PREC_FP64: everything in FP64.  Where the grid allows it (N >= 16,
+       the products of each row of pairs within 16 consecutive bins, N <= 400)
+       16 cells advance together and the gain sum runs on FP64 matrix cores;
+       otherwise one workgroup per cell.  The environment variable
+       COAG_STEP_KERNEL=cell, read by coag_create, forces the latter.
+     COAG_PREC_SPLIT_BF16: the gain sum sum_p n_i n_j K_p D_pk runs as BF16
+       matrix products of three-limb splits of its FP32-rounded operands with
+       FP32 accumulation; losses, fragments, stage states, error control, the
+       update and the per-cell mass bookkeeping stay in FP64.  Needs the same
+       grid conditions (else COAG_ENOTSUP).
    Errors: COAG_EINVAL (null pointer, C < 0, dt <= 0, rtol <= 0, max_sub < 1,
-   unknown mode or precision), COAG_ENOMEM. */
-int coag_step(coag_ctx *ctx, int64_t C, double *rho, const double *Kc, const double *Kf,
+   unknown mode or precision, rates_f32 without split precision), COAG_ENOTSUP,
+   COAG_ENOMEM. */
+int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void *Kf,
               double dt, double *h, const coag_tol *tol, int32_t *nsub, int32_t *nrej,
               double *h_log, int32_t *status, void *stream);
 
@@ -188,8 +209,9 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const double *Kc, const dou
      g_vfrag [C]    DEVICE out   dJ/dv_frag,c (through p_frag)
    Inputs rho_in [C][N], cells, v_dust, v_frag as for coag_rates; h_log
    [C][log_stride], nsub [C] DEVICE.  The stage states are recomputed from
-   rho_in.  prec: COAG_PREC_* of the contraction used in the recomputation and
-   the reverse sweep.  Errors: COAG_EINVAL, COAG_ENOMEM. */
+   rho_in.  prec: COAG_PREC_FP64 (the adjoint runs in FP64 only;
+   COAG_PREC_SPLIT_BF16 returns COAG_ENOTSUP).  Errors: COAG_EINVAL,
+   COAG_ENOTSUP, COAG_ENOMEM. */
 int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coag_cells *cells,
                        const double *v_dust, const double *v_frag, const double *h_log,
                        int32_t log_stride, const int32_t *nsub, const double *g_out,

@@ -37,7 +37,7 @@ class Cells(ct.Structure):
 class Tol(ct.Structure):
     _fields_ = [("rtol", ct.c_double), ("atol_rel", ct.c_double), ("h_min_rel", ct.c_double),
                 ("max_sub", ct.c_int32), ("mode", ct.c_int32), ("prec", ct.c_int32),
-                ("renorm", ct.c_int32)]
+                ("renorm", ct.c_int32), ("rates_f32", ct.c_int32)]
 
 
 class CoagError(RuntimeError):
@@ -66,6 +66,7 @@ def load():
         "coag_destroy": (None, [_vp]),
         "coag_last_error": (ct.c_char_p, [_vp]),
         "coag_rates": (ct.c_int, [_vp, i64, P(Cells), _vp, _vp, _vp, _vp, _vp]),
+        "coag_rates_f32": (ct.c_int, [_vp, i64, P(Cells), _vp, _vp, _vp, _vp, _vp]),
         "coag_rhs": (ct.c_int, [_vp, i64, _vp, _vp, _vp, _vp, _vp]),
         "coag_step": (ct.c_int, [_vp, i64, _vp, _vp, _vp, ct.c_double, _vp, P(Tol), _vp, _vp,
                                  _vp, _vp, _vp]),
@@ -83,7 +84,7 @@ def header_symbols():
     """Function names declared in include/coag.h."""
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(coag_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(coag_[a-z0-9_]+)\s*\(", src)))
 
 
 def check(rc, ctx=None):

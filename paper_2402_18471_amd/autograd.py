@@ -1,8 +1,9 @@
 """torch.autograd.Function around repeated coagulation calls, with the
 hand-written adjoint of libcoag (coag_step_backward) as its backward.
 
-Forward: n_steps calls of coag_rates + coag_step (ADAPTIVE), recording each
-call's accepted step sizes and keeping the state every `ckpt_every` calls.
+Forward: n_steps calls of coag_rates + coag_step (ADAPTIVE, or FIXED with
+`fixed_nsub` equal sub-steps per call), recording each call's accepted step
+sizes and keeping the state every `ckpt_every` calls.
 Backward: for each checkpoint segment, from the last to the first, the
 segment is recomputed from its checkpoint with the recorded step sizes
 (REPLAY, so the step sequence is exactly the one the forward pass took) and
@@ -20,7 +21,7 @@ from . import _lib as L
 class CoagStep(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rho0, alpha, v_frag, coag, cells, v_dust, dt, n_steps, ckpt_every=20,
-                prec=L.PREC_FP64, max_sub=64, rtol=1e-2, atol_rel=1e-10):
+                prec=L.PREC_FP64, max_sub=64, fixed_nsub=None, rtol=1e-2, atol_rel=1e-10):
         C = rho0.shape[0]
         dev = rho0.device
         cells = dict(cells)
@@ -31,11 +32,16 @@ class CoagStep(torch.autograd.Function):
         logs = torch.zeros((n_steps, C, max_sub), dtype=torch.float64, device=dev)
         nsubs = torch.zeros((n_steps, C), dtype=torch.int32, device=dev)
         ckpts = []
+        mode = L.ADAPTIVE if fixed_nsub is None else L.FIXED
+        if fixed_nsub is not None:
+            if not 1 <= int(fixed_nsub) <= max_sub:
+                raise ValueError("fixed_nsub must lie in [1, max_sub]")
+            nsubs.fill_(int(fixed_nsub))
         for s in range(n_steps):
             if s % ckpt_every == 0:
                 ckpts.append(rho.clone())
             Kc, Kf = coag.coag_rates(cells, v_dust, vf)
-            r = coag.coag_step(rho, Kc, Kf, dt, h=h, mode=L.ADAPTIVE, prec=prec, rtol=rtol,
+            r = coag.coag_step(rho, Kc, Kf, dt, h=h, mode=mode, prec=prec, rtol=rtol,
                                atol_rel=atol_rel, max_sub=max_sub, nsub=nsubs[s], h_log=logs[s])
             st = r["status"]
             if bool((st != 0).any()):
@@ -72,11 +78,11 @@ class CoagStep(torch.autograd.Function):
                 g = gi
                 g_alpha += ga
                 g_vfrag += gv
-        return (g, g_alpha, g_vfrag) + (None,) * 10
+        return (g, g_alpha, g_vfrag) + (None,) * 11
 
 
 def coag_evolve(coag, rho0, alpha, v_frag, cells, v_dust, dt, n_steps, ckpt_every=20,
-                prec=L.PREC_FP64, max_sub=64):
+                prec=L.PREC_FP64, max_sub=64, fixed_nsub=None):
     """Differentiable n_steps coagulation calls (see CoagStep)."""
     return CoagStep.apply(rho0, alpha, v_frag, coag, cells, v_dust, dt, n_steps, ckpt_every,
-                          prec, max_sub)
+                          prec, max_sub, fixed_nsub)

@@ -1,5 +1,5 @@
 """Python face of libcoag with the C ABI's names (coag_mass_grid, coag_create,
-coag_rates, coag_rhs, coag_step, coag_step_backward).
+coag_rates, coag_rates_f32, coag_rhs, coag_step, coag_step_backward).
 
 Tensors are torch CUDA (HIP) tensors, float64 (int32 for counters), contiguous;
 torch supplies device memory and the current stream, nothing else.
@@ -95,6 +95,20 @@ class CoagContext:
                                          _ptr(Kc), _ptr(Kf), _stream()))
         return Kc, Kf
 
+    def coag_rates_f32(self, cells, v_dust, v_frag, Kc=None, Kf=None):
+        """The rates rounded to float32, for split-precision steps."""
+        C = int(v_frag.shape[0])
+        cs, keep = self._cells(cells, C)
+        _dev(v_dust, shape=(C, self.N, 3), name="v_dust")
+        _dev(v_frag, shape=(C,), name="v_frag")
+        dev = v_frag.device
+        f32 = torch.float32
+        Kc = torch.empty((C, self.P), dtype=f32, device=dev) if Kc is None else _dev(Kc, f32, (C, self.P), "Kc")
+        Kf = torch.empty((C, self.P), dtype=f32, device=dev) if Kf is None else _dev(Kf, f32, (C, self.P), "Kf")
+        self._check(self._lib.coag_rates_f32(self._h, C, ct.byref(cs), _ptr(v_dust), _ptr(v_frag),
+                                             _ptr(Kc), _ptr(Kf), _stream()))
+        return Kc, Kf
+
     def coag_rhs(self, rho, Kc, Kf, out=None):
         C = int(rho.shape[0])
         _dev(rho, shape=(C, self.N), name="rho")
@@ -107,12 +121,16 @@ class CoagContext:
     def coag_step(self, rho, Kc, Kf, dt, h=None, mode=L.ADAPTIVE, prec=L.PREC_FP64, rtol=1e-2,
                   atol_rel=1e-10, h_min_rel=1e-12, max_sub=10000, renorm=False, nsub=None,
                   h_log=None, log=True):
-        """Advances rho (in place) by dt; returns dict(rho, h, nsub, nrej, h_log, status)."""
+        """Advances rho (in place) by dt; returns dict(rho, h, nsub, nrej, h_log, status).
+        Kc, Kf: float64 from coag_rates, or float32 from coag_rates_f32 (split
+        precision only)."""
         C = int(rho.shape[0])
         dev = rho.device
         _dev(rho, shape=(C, self.N), name="rho")
-        _dev(Kc, shape=(C, self.P), name="Kc")
-        _dev(Kf, shape=(C, self.P), name="Kf")
+        rates_f32 = Kc.dtype == torch.float32
+        rdt = torch.float32 if rates_f32 else torch.float64
+        _dev(Kc, dtype=rdt, shape=(C, self.P), name="Kc")
+        _dev(Kf, dtype=rdt, shape=(C, self.P), name="Kf")
         if h is None:
             h = torch.zeros(C, dtype=torch.float64, device=dev)
         _dev(h, shape=(C,), name="h")
@@ -129,7 +147,8 @@ class CoagContext:
             _dev(h_log, shape=(C, max_sub), name="h_log")
         nrej = torch.zeros(C, dtype=torch.int32, device=dev)
         status = torch.zeros(C, dtype=torch.int32, device=dev)
-        tol = L.Tol(rtol, atol_rel, h_min_rel, max_sub, mode, prec, 1 if renorm else 0)
+        tol = L.Tol(rtol, atol_rel, h_min_rel, max_sub, mode, prec, 1 if renorm else 0,
+                    1 if rates_f32 else 0)
         self._check(self._lib.coag_step(self._h, C, _ptr(rho), _ptr(Kc), _ptr(Kf), float(dt),
                                         _ptr(h), ct.byref(tol), _ptr(nsub), _ptr(nrej),
                                         _ptr(h_log), _ptr(status), _stream()))

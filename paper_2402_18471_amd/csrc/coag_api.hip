@@ -1,18 +1,20 @@
 // coag_api.hip -- the C ABI of libcoag (declared in include/coag.h): argument
 // validation on the host, context lifetime, workspaces and kernel launches.
-// Every numerical step of the path runs in the kernels of coag_kernels.hip and
-// coag_split.hip; this file only checks, allocates and launches.
+// Every numerical step of the path runs in the kernels of coag_kernels.hip,
+// coag_step2.hip and coag_batch.hip; this file only checks, allocates and
+// launches.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
 
 #include "../../include/coag.h"
 #include "coag_launch.h"
-#include "coag_split.h"
+#include "coag_batch.h"
 
 using namespace coag;
 
@@ -24,7 +26,8 @@ struct coag_ctx {
     // device tables
     void *block = nullptr;                 // one allocation holding every table
     Tables T{};
-    SplitTables S{};
+    BatchTables B{};
+    bool batch_fp64 = true;                // FP64 steps take the batched kernel when it applies
     // grow-only workspaces
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -138,8 +141,8 @@ int coag_create(const coag_grid *g, coag_ctx **out) {
                  o_rw1 = take(8 * P), o_fm = take(8 * P);
     const size_t o_m = take(8 * N), o_s = take(8 * N), o_dE = take(8 * N), o_iE = take(8 * N),
                  o_me = take(8 * (N + 1)), o_idm = take(8 * N), o_fc = take(4 * N),
-                 o_fr = take(4 * N);
-    const size_t o_split = take(split_tables_bytes(N));
+                 o_fr = take(4 * N), o_cd = take(4 * N), o_rd = take(4 * N);
+    const size_t o_batch = take(batch_tables_bytes(N));
     if (hipMalloc(&ctx->block, off) != hipSuccess) {
         (void)hipGetLastError();
         delete ctx;
@@ -164,6 +167,8 @@ int coag_create(const coag_grid *g, coag_ctx **out) {
     T.invdm = (double *)(b + o_idm);
     T.fcol = (int *)(b + o_fc);
     T.frow = (int *)(b + o_fr);
+    T.cdiag = (int *)(b + o_cd);
+    T.rdiag = (int *)(b + o_rd);
     T.chi = g->chi;
     T.split = g->split;
     double *me = (double *)(b + o_me);
@@ -175,9 +180,12 @@ int coag_create(const coag_grid *g, coag_ctx **out) {
         e = launch_build(N, T.m, me, g->eta, g->chi, g->split, (uint32_t *)T.pij,
                          (uint32_t *)T.dst, (double *)T.cw0, (double *)T.cw1, (double *)T.rw0,
                          (double *)T.rw1, (double *)T.fm, (double *)T.dE, (double *)T.invE,
-                         (double *)T.invdm, (int *)T.fcol, (int *)T.frow, nullptr);
-    if (e == hipSuccess) e = build_split_tables(T, b + o_split, &ctx->S, nullptr);
+                         (double *)T.invdm, (int *)T.fcol, (int *)T.frow, (int *)T.cdiag,
+                         (int *)T.rdiag, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = build_batch_tables(T, b + o_batch, &ctx->B);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (const char *k = getenv("COAG_STEP_KERNEL")) ctx->batch_fp64 = strcmp(k, "cell") != 0;
     if (e != hipSuccess) rc = fail(nullptr, COAG_EHIP, "coag_create: %s", hipGetErrorString(e));
     if (rc != COAG_OK) {
         (void)hipFree(ctx->block);
@@ -227,6 +235,21 @@ int coag_rates(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *
     return COAG_OK;
 }
 
+int coag_rates_f32(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
+                   const double *v_frag, float *Kc, float *Kf, void *stream) {
+    if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_rates_f32: ctx is NULL");
+    if (C < 0 || C > 0x7fffffff)
+        return fail(ctx, COAG_EINVAL, "coag_rates_f32: bad C = %lld", (long long)C);
+    if (C == 0) return COAG_OK;
+    if (int r = check_cells(ctx, cells)) return r;
+    if (!v_dust || !v_frag || !Kc || !Kf)
+        return fail(ctx, COAG_EINVAL, "coag_rates_f32: NULL array");
+    if (int r = set_device(ctx)) return r;
+    HIP_TRY(ctx, launch_rates_f32(ctx->T, C, cell_arrays(cells), v_dust, v_frag, Kc, Kf,
+                                  (hipStream_t)stream));
+    return COAG_OK;
+}
+
 int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, const double *Kf,
              double *drho_dt, void *stream) {
     if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_rhs: ctx is NULL");
@@ -241,7 +264,7 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
     return COAG_OK;
 }
 
-int coag_step(coag_ctx *ctx, int64_t C, double *rho, const double *Kc, const double *Kf,
+int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void *Kf,
               double dt, double *h, const coag_tol *tol, int32_t *nsub, int32_t *nrej,
               double *h_log, int32_t *status, void *stream) {
     if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_step: ctx is NULL");
@@ -255,6 +278,14 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const double *Kc, const dou
     if (tol->prec != COAG_PREC_FP64 && tol->prec != COAG_PREC_SPLIT_BF16)
         return fail(ctx, COAG_EINVAL, "coag_step: unknown precision %d", tol->prec);
     if (tol->max_sub < 1) return fail(ctx, COAG_EINVAL, "coag_step: max_sub must be >= 1");
+    if (tol->rates_f32 != 0 && tol->rates_f32 != 1)
+        return fail(ctx, COAG_EINVAL, "coag_step: rates_f32 must be 0 or 1");
+    if (tol->rates_f32 && tol->prec != COAG_PREC_SPLIT_BF16)
+        return fail(ctx, COAG_EINVAL, "coag_step: FP32 rates need COAG_PREC_SPLIT_BF16");
+    if (tol->prec == COAG_PREC_SPLIT_BF16 && !batch_available(ctx->T, ctx->B))
+        return fail(ctx, COAG_ENOTSUP,
+                    "coag_step: the split-BF16 step needs N >= 16 bins whose products of each "
+                    "row fit a 16-bin window, and N <= 400");
     if (tol->mode == COAG_ADAPTIVE) {
         if (!h && C > 0) return fail(ctx, COAG_EINVAL, "coag_step: h is required in ADAPTIVE mode");
         if (!(tol->rtol > 0.0) || !(tol->atol_rel >= 0.0) || !(tol->h_min_rel >= 0.0))
@@ -266,8 +297,8 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const double *Kc, const dou
     if (int r = set_device(ctx)) return r;
     StepArgs a;
     a.rho = rho;
-    a.Kc = Kc;
-    a.Kf = Kf;
+    a.Kc = (const double *)Kc;
+    a.Kf = (const double *)Kf;
     a.dt = dt;
     a.h = h;
     a.rtol = tol->rtol;
@@ -280,10 +311,11 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const double *Kc, const dou
     a.nrej = nrej;
     a.status = status;
     a.h_log = h_log;
-    if (tol->prec == COAG_PREC_SPLIT_BF16) {
-        const size_t need = split_step_ws_bytes(ctx->N, C);
-        if (int r = ensure_ws(ctx, need)) return r;
-        HIP_TRY(ctx, launch_step_split(ctx->T, ctx->S, C, a, ctx->ws, (hipStream_t)stream));
+    const bool split = tol->prec == COAG_PREC_SPLIT_BF16;
+    if (split || (ctx->batch_fp64 && batch_available(ctx->T, ctx->B))) {
+        if (int r = ensure_ws(ctx, batch_ws_bytes(ctx->N, C))) return r;
+        HIP_TRY(ctx, launch_step_batch(ctx->T, ctx->B, C, a, split ? 1 : 0, tol->rates_f32,
+                                       (double *)ctx->ws, (hipStream_t)stream));
     } else if (reg_path_available(ctx->N)) {
         HIP_TRY(ctx, launch_step2(ctx->T, C, a, (hipStream_t)stream));
     } else {
@@ -302,20 +334,18 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
         return fail(ctx, COAG_EINVAL, "coag_step_backward: bad C = %lld", (long long)C);
     if (prec != COAG_PREC_FP64 && prec != COAG_PREC_SPLIT_BF16)
         return fail(ctx, COAG_EINVAL, "coag_step_backward: unknown precision %d", prec);
+    if (prec == COAG_PREC_SPLIT_BF16)
+        return fail(ctx, COAG_ENOTSUP, "coag_step_backward: the adjoint runs in FP64 only");
     if (log_stride < 1) return fail(ctx, COAG_EINVAL, "coag_step_backward: log_stride must be >= 1");
     if (C == 0) return COAG_OK;
     if (int r = check_cells(ctx, cells)) return r;
     if (!rho_in || !v_dust || !v_frag || !h_log || !nsub || !g_out || !g_in || !g_alpha || !g_vfrag)
         return fail(ctx, COAG_EINVAL, "coag_step_backward: NULL array");
-    if (log_stride < 1) return fail(ctx, COAG_EINVAL, "coag_step_backward: log_stride must be >= 1");
-    if (prec != COAG_PREC_FP64 && prec != COAG_PREC_SPLIT_BF16)
-        return fail(ctx, COAG_EINVAL, "coag_step_backward: unknown precision %d", prec);
     if (int r = set_device(ctx)) return r;
     const size_t P = ctx->P, N = ctx->N;
     const size_t bK = align256(8 * P * (size_t)C);
     const size_t bY = align256(8 * N * (size_t)(log_stride + 1) * (size_t)C);
-    const size_t split_extra = prec == COAG_PREC_SPLIT_BF16 ? split_adjoint_ws_bytes(ctx->N, C) : 0;
-    if (int r = ensure_ws(ctx, 4 * bK + bY + split_extra)) return r;
+    if (int r = ensure_ws(ctx, 4 * bK + bY)) return r;
     char *w = (char *)ctx->ws;
     double *Kc = (double *)w, *Kf = (double *)(w + bK), *gKc = (double *)(w + 2 * bK),
            *gKf = (double *)(w + 3 * bK), *Ys = (double *)(w + 4 * bK);
@@ -334,12 +364,7 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
     a.nsub = nsub;
     a.g_out = g_out;
     a.g_in = g_in;
-    if (prec == COAG_PREC_SPLIT_BF16) {
-        HIP_TRY(ctx, launch_adjoint_split(ctx->T, ctx->S, C, a, ca, v_dust, v_frag, g_alpha,
-                                          g_vfrag, w + 4 * bK + bY, st));
-    } else {
-        HIP_TRY(ctx, launch_adjoint(ctx->T, C, a, ca, v_dust, v_frag, g_alpha, g_vfrag, st));
-    }
+    HIP_TRY(ctx, launch_adjoint(ctx->T, C, a, ca, v_dust, v_frag, g_alpha, g_vfrag, st));
     return COAG_OK;
 }
 

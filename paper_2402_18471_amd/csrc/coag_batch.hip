@@ -1,0 +1,605 @@
+// coag_batch.hip -- cell-batched BS3(2) step with the gain contraction on the
+// matrix cores.
+//
+// A workgroup (8 waves) advances a batch of 16 cells in lockstep: every
+// right-hand side of eq. `smol` is evaluated for the 16 cells together, so
+// that the gain sum G[cell, k] = sum_p R[cell, p] D[p, k] (R = n_i n_j K, D the
+// fixed redistribution tensor of eqs. `Cijk`, `Rijk`) is a matrix product
+// with the cells as its M dimension.  Pairs are taken in chunks of 16 of one
+// row i (K = 32: the coagulating and the fragmenting rate of each pair); all
+// coagulation and remnant products of row i, and the loss m_i of the heavier
+// grain, land in a 16-bin window, the N dimension.  D is stored per chunk as
+// MFMA B operands (FP64, or three BF16 limbs).
+//
+// What is not a matrix product stays on the vector units in FP64: the loss of
+// the lighter grain m_j (a column sum), the fragment mass deposited at the top
+// fragment bin (the accumulation of Rafikov et al. 2020, eq. `Nijk`), the
+// fragment suffix sum, stage states, error control and the update.
+//
+// Split-BF16 form: the chunk operand A = n_j K / max_k n_k is rounded to FP32
+// and split into three BF16 limbs a0 + a1 + a2 (each the rounding of what the
+// previous ones leave), D likewise; the six limb products of order <= 2 are
+// accumulated in FP32 by v_mfma_f32_16x16x32_bf16 and scaled back
+// (x n_i max_k n_k) into the FP64 accumulators when the row changes.  The
+// total mass of each cell is restored in FP64 at the end of the call.
+//
+// Cells of a batch that have finished (or lie past C) contribute zero rates
+// and take no updates; the batch stops when every cell has.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "coag_batch.h"
+
+namespace coag {
+
+namespace {
+
+constexpr int kBC = kBatchCells;
+constexpr int kBWaves = 8;
+constexpr int kBBlock = 64 * kBWaves;
+constexpr int kWin = 16;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// round-to-nearest-even BF16 limbs of x: x = a0 + a1 + a2 + O(2^-25 |x|)
+struct Limbs {
+    __bf16 a0, a1, a2;
+};
+__device__ __forceinline__ Limbs split3(float x) {
+    Limbs L;
+    L.a0 = (__bf16)x;
+    const float r1 = x - (float)L.a0;
+    L.a1 = (__bf16)r1;
+    const float r2 = r1 - (float)L.a1;
+    L.a2 = (__bf16)r2;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// tables
+// ---------------------------------------------------------------------------
+int n_chunks(int N) {
+    int nc = 0;
+    for (int i = 0; i < N; ++i) nc += (i + 1 + 15) / 16;
+    return nc;
+}
+
+// D entry of pair (i, j), kind (0 coagulation, 1 fragmentation), bin: the mass
+// put into the bin per unit rate minus m_i for bin i (the heavier grain's loss)
+__device__ double d_entry(const Tables &T, int i, int j, int kind, int bin) {
+    if (j > i) return 0.0;
+    const long p = (long)i * (i + 1) / 2 + j;
+    const uint32_t d = T.dst[p];
+    double v = 0.0;
+    if (kind == 0) {
+        const int c = d & 1023;
+        if (bin == c) v += T.cw0[p];
+        if (bin == c + 1) v += T.cw1[p];
+    } else {
+        const int r = (d >> 10) & 1023;
+        if (bin == r) v += T.rw0[p];
+        if (bin == r + 1) v += T.rw1[p];
+    }
+    if (bin == i) v -= T.m[i];
+    return v;
+}
+
+// window of each row: the highest target minus 15, clipped to [0, N - 16]
+__global__ void k_batch_rows(Tables T, int *wb, int *bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= T.N) return;
+    const int N = T.N;
+    int lo = i, hi = i;
+    for (int j = 0; j <= i; ++j) {
+        const long p = (long)i * (i + 1) / 2 + j;
+        const uint32_t d = T.dst[p];
+        const int c = d & 1023, r = (d >> 10) & 1023;
+        if (T.cw0[p] != 0.0) { lo = min(lo, c); hi = max(hi, c); }
+        if (T.cw1[p] != 0.0) { lo = min(lo, c + 1); hi = max(hi, c + 1); }
+        if (T.rw0[p] != 0.0) { lo = min(lo, r); hi = max(hi, r); }
+        if (T.rw1[p] != 0.0) { lo = min(lo, r + 1); hi = max(hi, r + 1); }
+    }
+    int b = hi - (kWin - 1);
+    if (b > N - kWin) b = N - kWin;
+    if (b < 0) b = 0;
+    wb[i] = b;
+    if (lo < b || hi >= b + kWin) atomicOr(bad, 1);
+}
+
+// one thread per (chunk, lane): the B operands that lane holds for the chunk
+__global__ void k_batch_b(Tables T, int NC, const int *crow, const int *wb, double *b64,
+                          uint4 *b16) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)NC * 64) return;
+    const int ch = (int)(t >> 6), lane = (int)(t & 63);
+    const int i = crow[ch] & 0xffff, q = crow[ch] >> 16;
+    const int g = lane >> 4, bin = wb[i] + (lane & 15);
+    // FP64 operand of MFMA s: K row g <-> pair 16q + 4g + s % 4, kind s / 4
+    for (int s = 0; s < 8; ++s)
+        b64[((long)ch * 8 + s) * 64 + lane] = d_entry(T, i, 16 * q + 4 * g + (s & 3), s >> 2, bin);
+    // BF16 operand: K rows 8g + e <-> pair 16q + 8 (g % 2) + e, kind g / 2
+    union {
+        __bf16 h[8];
+        uint4 u;
+    } L0, L1, L2;
+    for (int e = 0; e < 8; ++e) {
+        const Limbs L = split3((float)d_entry(T, i, 16 * q + 8 * (g & 1) + e, g >> 1, bin));
+        L0.h[e] = L.a0;
+        L1.h[e] = L.a1;
+        L2.h[e] = L.a2;
+    }
+    b16[((long)ch * 3 + 0) * 64 + lane] = L0.u;
+    b16[((long)ch * 3 + 1) * 64 + lane] = L1.u;
+    b16[((long)ch * 3 + 2) * 64 + lane] = L2.u;
+}
+
+// ---------------------------------------------------------------------------
+// per-cell control (one entry per cell of the batch, in LDS)
+// ---------------------------------------------------------------------------
+struct Ctl {
+    double h, t, hh, mass0, atol, nmax, inv_nmax, fac;
+    int nacc, nrej, status, nfix, clipped, active, live, pad;
+};
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int PREC, typename RT>
+__global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B, StepArgs a,
+                                                        long C, double *ws) {
+    extern __shared__ double lds[];
+    const int N = T.N;
+    const long P = T.P;
+    const long cell0 = (long)blockIdx.x * kBC;
+    double *nv = lds, *net = lds + kBC * N, *phi = lds + 2 * kBC * N;
+    Ctl *ctl = (Ctl *)(lds + 3 * kBC * N);
+    int *flag = (int *)(ctl + kBC);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool adaptive = a.mode == 0;
+    const double dt = a.dt;
+    // workspace of cell c: k1, k2, k3, k4, yn, each [N]
+    auto wsp = [&](int c, int v) { return ws + ((cell0 + c) * 5 + v) * (long)N; };
+
+    // ---- set-up: each wave owns cells wv and wv + 8 ----
+    for (int u = 0; u < 2; ++u) {
+        const int c = wv + 8 * u;
+        const long gc = cell0 + c;
+        const bool live = gc < C;
+        double ms = 0.0;
+        if (live)
+            for (int k = lane; k < N; k += 64) ms += a.rho[gc * N + k];
+        ms = wave_sum_d(ms);
+        if (lane == 0) {
+            Ctl &s = ctl[c];
+            s.live = live;
+            s.active = live;
+            s.mass0 = ms;
+            s.atol = a.atol_rel * ms;
+            s.nacc = s.nrej = s.status = 0;
+            s.nfix = 0;
+            s.t = 0.0;
+            s.hh = 0.0;
+            s.clipped = 0;
+            s.h = 0.0;
+            if (live) {
+                if (adaptive) {
+                    s.h = a.h[gc] > 0.0 ? a.h[gc] : dt;
+                } else {
+                    s.nfix = a.nsub[gc];
+                    if (s.nfix < 0 || s.nfix > a.max_sub) {
+                        s.status = 2;
+                        s.nfix = 0;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- helpers ----
+    // state of stage `stage` of cell c at bin k (0: y, 2, 3: stage states, 4: y+)
+    auto form = [&](int stage) {
+        for (int u = 0; u < 2; ++u) {
+            const int c = wv + 8 * u;
+            const long gc = cell0 + c;
+            const bool on = stage == 0 ? ctl[c].live : ctl[c].active;
+            double mx = 0.0;
+            if (on) {
+                const double hh = ctl[c].hh;
+                const double *y = a.rho + gc * N;
+                const double *k1 = wsp(c, 0), *k2 = wsp(c, 1), *k3 = wsp(c, 2);
+                double *yn = wsp(c, 4);
+                for (int k = lane; k < N; k += 64) {
+                    double x;
+                    if (stage == 0) x = y[k];
+                    else if (stage == 2) x = y[k] + 0.5 * hh * k1[k];
+                    else if (stage == 3) x = y[k] + 0.75 * hh * k2[k];
+                    else {
+                        x = y[k] + hh * (2.0 / 9.0 * k1[k] + 1.0 / 3.0 * k2[k] + 4.0 / 9.0 * k3[k]);
+                        yn[k] = x;
+                    }
+                    const double n = x / T.m[k];
+                    nv[c * N + k] = n;
+                    mx = fmax(mx, fabs(n));
+                }
+            } else {
+                for (int k = lane; k < N; k += 64) nv[c * N + k] = 0.0;
+            }
+            for (int k = lane; k < N; k += 64) {
+                net[c * N + k] = 0.0;
+                phi[c * N + k] = 0.0;
+            }
+            if (PREC == 1) {
+                mx = wave_max_d(mx);
+                if (lane == 0) {
+                    ctl[c].nmax = mx;
+                    ctl[c].inv_nmax = mx > 0.0 ? 1.0 / mx : 0.0;
+                }
+            }
+        }
+    };
+
+    // gain and loss of all 16 cells into net (gain - loss without the
+    // fragment distribution) and phi (fragment mass per top bin)
+    auto contract = [&]() {
+        const int cl = lane & 15, g = lane >> 4;
+        const long cb = cell0 + cl < C ? cell0 + cl : C - 1;
+        const int NC = B.NC;
+        const int c0 = (int)((long)wv * NC / kBWaves), c1 = (int)((long)(wv + 1) * NC / kBWaves);
+        const double *nrow = nv + cl * N;
+        double *netc = net + cl * N, *phic = phi + cl * N;
+        const double inv_nmax = PREC == 1 ? ctl[cl].inv_nmax : 0.0;
+        int cur = -1;
+        f64x4 acc64 = {0.0, 0.0, 0.0, 0.0};
+        f32x4 acc32 = {0.0f, 0.0f, 0.0f, 0.0f};
+        auto flush = [&](int i) {
+            const int bin = B.wb[i] + cl;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = 4 * g + r;
+                if (PREC == 0) {
+                    atomicAdd(&net[c * N + bin], acc64[r]);
+                } else {
+                    const double f = nv[c * N + i] * ctl[c].nmax;
+                    atomicAdd(&net[c * N + bin], f * (double)acc32[r]);
+                }
+            }
+        };
+        for (int ch = c0; ch < c1; ++ch) {
+            const int cr = B.crow[ch];
+            const int i = cr & 0xffff, q = cr >> 16;
+            if (i != cur) {
+                if (cur >= 0) flush(cur);
+                cur = i;
+                acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
+                acc32 = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+            const long prow = (long)i * (i + 1) / 2;
+            const double ni = nrow[i];
+            if (PREC == 0) {
+                const RT *Kc = (const RT *)a.Kc + cb * P, *Kf = (const RT *)a.Kf + cb * P;
+                double rc[4], rf[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int j = 16 * q + 4 * g + s;
+                    const bool ok = j <= i;
+                    const int jc = ok ? j : i;
+                    const long p = prow + jc;
+                    const double nn = ok ? ni * nrow[jc] : 0.0;
+                    rc[s] = nn * (double)Kc[p];
+                    rf[s] = nn * (double)Kf[p];
+                    atomicAdd(&netc[jc], -T.m[jc] * (rc[s] + rf[s]));
+                    atomicAdd(&phic[T.dst[p] >> 20], T.fm[p] * rf[s]);
+                }
+                const double *bt = B.b64 + (long)ch * 8 * 64 + lane;
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rc[s], bt[s * 64], acc64, 0, 0, 0);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rf[s], bt[(4 + s) * 64], acc64, 0,
+                                                                 0, 0);
+            } else {
+                const int kind = g >> 1;
+                const RT *K = (const RT *)(kind ? a.Kf : a.Kc) + cb * P;
+                union {
+                    __bf16 h[8];
+                    bf16x8 v;
+                } A0, A1, A2;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int j = 16 * q + 8 * (g & 1) + e;
+                    const bool ok = j <= i;
+                    const int jc = ok ? j : i;
+                    const long p = prow + jc;
+                    const double t = ok ? nrow[jc] * (double)K[p] : 0.0;
+                    const double r = ni * t;
+                    atomicAdd(&netc[jc], -T.m[jc] * r);
+                    if (kind) atomicAdd(&phic[T.dst[p] >> 20], T.fm[p] * r);
+                    const Limbs L = split3((float)(t * inv_nmax));
+                    A0.h[e] = L.a0;
+                    A1.h[e] = L.a1;
+                    A2.h[e] = L.a2;
+                }
+                const uint4 *bt = B.b16 + (long)ch * 3 * 64 + lane;
+                union {
+                    uint4 u;
+                    bf16x8 v;
+                } B0, B1, B2;
+                B0.u = bt[0];
+                B1.u = bt[64];
+                B2.u = bt[128];
+                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0.v, B0.v, acc32, 0, 0, 0);
+                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0.v, B1.v, acc32, 0, 0, 0);
+                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1.v, B0.v, acc32, 0, 0, 0);
+                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0.v, B2.v, acc32, 0, 0, 0);
+                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1.v, B1.v, acc32, 0, 0, 0);
+                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2.v, B0.v, acc32, 0, 0, 0);
+            }
+        }
+        if (cur >= 0) flush(cur);
+    };
+
+    // slope of cell c: net + dE_k sum_{l >= k} phi_l invE_l, into ws slot v
+    auto finish = [&](int stage, int v) {
+        for (int u = 0; u < 2; ++u) {
+            const int c = wv + 8 * u;
+            const bool on = stage == 0 ? ctl[c].live : ctl[c].active;
+            if (!on) continue;
+            double *out = wsp(c, v);
+            double carry = 0.0;
+            for (int top = N - 1; top >= 0; top -= 64) {
+                const int k = top - lane;
+                double x = k >= 0 ? phi[c * N + k] * T.invE[k] : 0.0;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const double y = __shfl_up(x, o, 64);
+                    if (lane >= o) x += y;
+                }
+                if (k >= 0) out[k] = net[c * N + k] + T.dE[k] * (x + carry);
+                carry += __shfl(x, 63, 64);
+            }
+        }
+    };
+
+    // set up the next attempt of cell c (owner wave, after a block barrier)
+    auto begin = [&](int c) {
+        Ctl &s = ctl[c];
+        if (!s.active) return;
+        bool go = true;
+        if (adaptive) {
+            if (!(s.t < dt)) go = false;
+            else if (s.nacc + s.nrej >= a.max_sub) { s.status = 2; go = false; }
+            else {
+                s.hh = s.h;
+                s.clipped = 0;
+                if (s.hh >= dt - s.t) { s.hh = dt - s.t; s.clipped = 1; }
+                if (!s.clipped && s.hh < a.h_min_rel * dt) { s.status = 1; go = false; }
+            }
+        } else {
+            if (s.nacc >= s.nfix) go = false;
+            else s.hh = a.mode == 1 ? dt / s.nfix : a.h_log[(cell0 + c) * (long)a.max_sub + s.nacc];
+        }
+        s.active = go;
+    };
+
+    // accept / reject the attempt of cell c (owner wave)
+    auto decide = [&](int c) {
+        Ctl &s = ctl[c];
+        if (!s.active) return;
+        const long gc = cell0 + c;
+        double *y = a.rho + gc * N;
+        const double *k1 = wsp(c, 0), *k2 = wsp(c, 1), *k3 = wsp(c, 2), *k4 = wsp(c, 3),
+                     *yn = wsp(c, 4);
+        bool accept = true;
+        double fac = 1.0;
+        const double hh = s.hh;
+        if (adaptive) {
+            double qmax = 0.0, ymin = INFINITY, bad = 0.0;
+            for (int k = lane; k < N; k += 64) {
+                const double e = hh * (-5.0 / 72.0 * k1[k] + 1.0 / 12.0 * k2[k] + 1.0 / 9.0 * k3[k] -
+                                       1.0 / 8.0 * k4[k]);
+                const double sc = s.atol + a.rtol * fmax(fabs(y[k]), fabs(yn[k]));
+                if (!isfinite(yn[k]) || !isfinite(e)) bad += 1.0;
+                qmax = fmax(qmax, fabs(e) / sc);
+                ymin = fmin(ymin, yn[k]);
+            }
+            bad = wave_sum_d(bad);
+            const double err = wave_max_d(qmax);
+            const double ylo = wave_min_d(ymin);
+            if (bad > 0.0 || !isfinite(err)) {
+                if (lane == 0) {
+                    s.status = 3;
+                    s.active = 0;
+                }
+                return;
+            }
+            fac = err == 0.0 ? 5.0 : 0.9 * pow(err, -1.0 / 3.0);
+            fac = fmin(5.0, fmax(0.2, fac));
+            accept = err <= 1.0 && !(ylo < -s.atol);
+            if (!accept && lane == 0) s.h = hh * (err <= 1.0 ? 0.5 : fac);
+        }
+        if (accept) {
+            for (int k = lane; k < N; k += 64) y[k] = yn[k];
+            double *k1w = wsp(c, 0);
+            for (int k = lane; k < N; k += 64) k1w[k] = k4[k];
+            if (lane == 0) {
+                if (a.h_log && s.nacc < a.max_sub && a.mode != 2)
+                    a.h_log[gc * (long)a.max_sub + s.nacc] = hh;
+                ++s.nacc;
+                if (adaptive) {
+                    s.t = s.clipped ? dt : s.t + hh;
+                    if (!s.clipped) s.h = hh * fac;
+                }
+            }
+        } else if (lane == 0) {
+            ++s.nrej;
+        }
+    };
+
+    // ---- the stage loop: 0 (k1 = f(y)), then 2, 3, 4 per attempt ----
+    int stage = 0;
+    while (true) {
+        form(stage);
+        __syncthreads();
+        contract();
+        __syncthreads();
+        finish(stage, stage == 0 ? 0 : stage - 1);
+        __syncthreads();
+        if (stage == 0 || stage == 4) {
+            if (stage == 4) {
+                decide(wv);
+                decide(wv + 8);
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) *flag = 0;
+            __syncthreads();
+            if (lane == 0) {
+                begin(wv);
+                begin(wv + 8);
+                if (ctl[wv].active || ctl[wv + 8].active) atomicOr(flag, 1);
+            }
+            __syncthreads();
+            if (!*flag) break;
+            stage = 2;
+        } else {
+            ++stage;
+        }
+    }
+
+    // ---- outputs; FP64 mass bookkeeping ----
+    for (int u = 0; u < 2; ++u) {
+        const int c = wv + 8 * u;
+        Ctl &s = ctl[c];
+        if (!s.live) continue;
+        const long gc = cell0 + c;
+        double *y = a.rho + gc * N;
+        if (!adaptive && s.status == 0) {
+            double bad = 0.0;
+            for (int k = lane; k < N; k += 64) bad += isfinite(y[k]) ? 0.0 : 1.0;
+            if (wave_sum_d(bad) > 0.0 && lane == 0) s.status = 3;
+        }
+        if ((a.renorm || PREC == 1) && s.status == 0) {
+            double ms = 0.0;
+            for (int k = lane; k < N; k += 64) ms += y[k];
+            const double m1 = wave_sum_d(ms);
+            if (m1 > 0.0) {
+                const double sc = s.mass0 / m1;
+                for (int k = lane; k < N; k += 64) y[k] *= sc;
+            }
+        }
+        if (lane == 0) {
+            if (adaptive) {
+                a.h[gc] = s.h;
+                a.nsub[gc] = s.nacc;
+            }
+            if (a.nrej) a.nrej[gc] = s.nrej;
+            a.status[gc] = s.status;
+        }
+    }
+}
+
+size_t batch_lds_bytes(int N) {
+    return (size_t)3 * kBC * N * sizeof(double) + kBC * sizeof(Ctl) + 64;
+}
+
+template <typename K>
+hipError_t allow_lds_b(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+}  // namespace
+
+size_t batch_tables_bytes(int N) {
+    const size_t NC = (size_t)n_chunks(N);
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return al(4 * NC) + al(4 * (size_t)N) + al(8 * NC * 8 * 64) + al(16 * NC * 3 * 64) + 256;
+}
+
+hipError_t build_batch_tables(const Tables &T, void *mem, BatchTables *B) {
+    const int N = T.N;
+    const int NC = n_chunks(N);
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    char *p = (char *)mem;
+    int *crow = (int *)p;
+    p += al(4 * (size_t)NC);
+    int *wb = (int *)p;
+    p += al(4 * (size_t)N);
+    double *b64 = (double *)p;
+    p += al(8 * (size_t)NC * 8 * 64);
+    uint4 *b16 = (uint4 *)p;
+    p += al(16 * (size_t)NC * 3 * 64);
+    int *bad = (int *)p;
+    B->NC = NC;
+    B->ok = 0;
+    B->crow = crow;
+    B->wb = wb;
+    B->b64 = b64;
+    B->b16 = b16;
+    if (N < kWin) return hipSuccess;                 // window wider than the grid: path off
+    int *h = (int *)malloc(sizeof(int) * NC);
+    if (!h) return hipErrorOutOfMemory;
+    int c = 0;
+    for (int i = 0; i < N; ++i)
+        for (int q = 0; q * 16 <= i; ++q) h[c++] = i | (q << 16);
+    hipError_t e = hipMemcpy(crow, h, sizeof(int) * NC, hipMemcpyHostToDevice);
+    free(h);
+    if (e == hipSuccess) e = hipMemset(bad, 0, sizeof(int));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_rows, dim3((N + 63) / 64), dim3(64), 0, 0, T, wb, bad);
+    hipLaunchKernelGGL(k_batch_b, dim3((unsigned)((NC * 64L + 255) / 256)), dim3(256), 0, 0, T, NC,
+                       crow, wb, b64, b16);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int hb = 1;
+    if ((e = hipMemcpy(&hb, bad, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) return e;
+    B->ok = hb == 0;
+    return hipSuccess;
+}
+
+bool batch_available(const Tables &T, const BatchTables &B) {
+    return B.ok && batch_lds_bytes(T.N) <= 160 * 1024;
+}
+
+size_t batch_ws_bytes(int N, long C) {
+    const long nb = (C + kBC - 1) / kBC;
+    return (size_t)nb * kBC * 5 * N * sizeof(double);
+}
+
+hipError_t launch_step_batch(const Tables &T, const BatchTables &B, long C, const StepArgs &a,
+                             int prec, int rates_f32, double *ws, hipStream_t st) {
+    if (C == 0) return hipSuccess;
+    if (!batch_available(T, B)) return hipErrorNotSupported;
+    const size_t bytes = batch_lds_bytes(T.N);
+    const dim3 grid((unsigned)((C + kBC - 1) / kBC)), block(kBBlock);
+#define LAUNCH(PR, RT)                                                                       \
+    do {                                                                                     \
+        if (hipError_t e = allow_lds_b(k_step_batch<PR, RT>, bytes)) return e;              \
+        hipLaunchKernelGGL((k_step_batch<PR, RT>), grid, block, bytes, st, T, B, a, C, ws); \
+    } while (0)
+    if (prec == 0) {
+        if (rates_f32) return hipErrorNotSupported;
+        LAUNCH(0, double);
+    } else if (rates_f32) {
+        LAUNCH(1, float);
+    } else {
+        LAUNCH(1, double);
+    }
+#undef LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace coag

@@ -34,6 +34,8 @@ struct Tables {
     const double *invdm;   // [N] 1 / (m_{k+1} - m_k)  (0 for the top bin)
     const int *fcol;       // [N] top fragment bin when the largest fragment is chi m_j
     const int *frow;       // [N] top fragment bin when the largest fragment is m_i
+    const int *cdiag;      // [N] lower bracketing bin of the product m_i + m_i
+    const int *rdiag;      // [N] lower bracketing bin of the remnant m_i - chi m_i (0 if none)
     double chi;            // excavated mass / impactor mass
     int split;             // 0 MASS, 1 NUMBER
 };

@@ -97,7 +97,7 @@ __device__ int top_fragment_bin(const double *me, int N, double x) {
 // largest fragment of chi m_k (cratering) and of m_k (target destroyed).
 __global__ void k_build_frag(int N, const double *__restrict__ m, const double *__restrict__ me,
                              double eta, double chi, double *dE, double *invE, double *invdm,
-                             int *fcol, int *frow) {
+                             int *fcol, int *frow, int *cdiag, int *rdiag) {
 #pragma clang fp contract(off)
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
@@ -108,47 +108,101 @@ __global__ void k_build_frag(int N, const double *__restrict__ m, const double *
     invdm[k] = k + 1 < N ? 1.0 / (m[k + 1] - m[k]) : 0.0;
     fcol[k] = top_fragment_bin(me, N, chi * m[k]);
     frow[k] = top_fragment_bin(me, N, m[k]);
+    // brackets of the diagonal pair (k, k): largest l with m_l <= x
+    auto below = [&](double x) {
+        int lo = 0, hi = N;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (m[mid] <= x) lo = mid; else hi = mid;
+        }
+        return lo;
+    };
+    cdiag[k] = below(m[k] + m[k]);
+    const double cm = chi * m[k];
+    const double mr = cm < m[k] ? m[k] - cm : 0.0;
+    rdiag[k] = mr >= m[0] ? below(mr) : 0;
 }
 
 // ---------------------------------------------------------------------------
-// Pair rates: one workgroup per cell; per-bin Stokes numbers and velocities in
-// LDS, one thread per pair (strided), coalesced writes of Kc, Kf.
+// Pair rates: one workgroup per cell, one thread per pair (strided), coalesced
+// writes of Kc, Kf.  Everything in the Ormel & Cuzzi expressions that depends
+// on one bin only is tabulated per cell in LDS first.  Stokes numbers grow
+// with grain size, so the heavier grain i of a pair is the one with the larger
+// Stokes number: St_1 = St_i, St* = clamp(y* St_i, Re^-1/2, 1) is a per-row
+// value, and per pair only (St_i - St_j) / (St_i + St_j) and
+// St_j^2 / (St* + St_j) remain to divide (plus v_frag / dv).
+//   A_k = St_k^2 / (1 + St_k),  B_k = St_k^2 / (St_k + delta),
+//   S_k = clamp(y* St_k, delta, 1),  C_k = St_k^2 / (S_k + St_k)
+//   dV_I^2  = (St_i - St_j)/(St_i + St_j) (C_i - A_i - q + A_j)
+//   dV_II^2 = 2 (S_i - delta) + C_i - B_i + q - B_j,   q = St_j^2 / (S_i + St_j)
 // ---------------------------------------------------------------------------
-template <int BLOCK>
+template <int BLOCK, typename OT>
 __global__ __launch_bounds__(BLOCK) void k_rates(Tables T, CellArrays cells,
                                                  const double *__restrict__ v_dust,
                                                  const double *__restrict__ v_frag,
-                                                 double *__restrict__ Kc, double *__restrict__ Kf) {
+                                                 OT *__restrict__ Kc, OT *__restrict__ Kf) {
     extern __shared__ double lds[];
     const int N = T.N, P = T.P;
     const long c = blockIdx.x;
-    double *St = lds, *vx = lds + N, *vy = lds + 2 * N, *vz = lds + 3 * N;
+    double *St = lds, *A = lds + N, *Bt = lds + 2 * N, *S = lds + 3 * N, *Ct = lds + 4 * N,
+           *vx = lds + 5 * N, *vy = lds + 6 * N, *vz = lds + 7 * N, *im = lds + 8 * N;
     const double rho_g = cells.rho_g[c], c_s = cells.c_s[c], Om = cells.Omega[c];
     const double v_th = sqrt(8.0 / M_PI) * c_s;
-    CellState cs;
-    cs.T = cells.T[c];
-    cs.c_s = c_s;
-    cs.alpha = cells.alpha[c];
-    cs.delta = 1.0 / sqrt(cs.alpha * c_s * cells.H[c] / cells.nu_mol[c]);
-    cs.v_frag = v_frag[c];
+    const double alpha = cells.alpha[c];
+    const bool turb = alpha > 0.0;
+    const double delta = turb ? 1.0 / sqrt(alpha * c_s * cells.H[c] / cells.nu_mol[c]) : 0.0;
+    const double vt_scale = alpha * c_s * c_s;
+    const double kbt = 8.0 * kBoltzmann * cells.T[c] / M_PI;
+    const double vf = v_frag[c];
     for (int k = threadIdx.x; k < N; k += BLOCK) {
-        St[k] = T.rho_m * T.s[k] / (rho_g * v_th) * Om;
+        const double st = T.rho_m * T.s[k] / (rho_g * v_th) * Om;
+        const double a = st * st;
+        St[k] = st;
+        A[k] = a / (1.0 + st);
+        double sk = kYStar * st;
+        if (sk < delta) sk = delta;
+        if (sk > 1.0) sk = 1.0;
+        S[k] = sk;
+        Bt[k] = turb ? a / (st + delta) : 0.0;
+        Ct[k] = a / (sk + st);
+        im[k] = 1.0 / T.m[k];
         const double *v = v_dust + (c * N + k) * 3;
         vx[k] = v[0];
         vy[k] = v[1];
         vz[k] = v[2];
     }
     __syncthreads();
-    double *kc = Kc + c * P, *kf = Kf + c * P;
+    OT *kc = Kc + c * P, *kf = Kf + c * P;
     for (int p = threadIdx.x; p < P; p += BLOCK) {
         const uint32_t ij = T.pij[p];
         const int i = pair_i(ij), j = pair_j(ij);
+        double vturb2 = 0.0;
+        if (turb) {
+            const double si = St[i], sj = St[j];
+            const double q = sj * sj / (S[i] + sj);
+            const double dV1 = (si - sj) / (si + sj) * (Ct[i] - A[i] - q + A[j]);
+            const double dV2 = 2.0 * (S[i] - delta) + Ct[i] - Bt[i] + q - Bt[j];
+            vturb2 = vt_scale * (dV1 + dV2);
+        }
         const double dx = vx[i] - vx[j], dy = vy[i] - vy[j], dz = vz[i] - vz[j];
-        const double vlam2 = dx * dx + dy * dy + dz * dz;
-        const PairRate r = pair_rate(cs, St[i], St[j], T.m[i], T.m[j], T.s[i], T.s[j], vlam2,
-                                     i == j ? 0.5 : 1.0);
-        kc[p] = r.Kc;
-        kf[p] = r.Kf;
+        const double dv = sqrt(kbt * (im[i] + im[j]) + vturb2 + (dx * dx + dy * dy + dz * dz));
+        const double ss = T.s[i] + T.s[j];
+        const double K = M_PI * ss * ss * dv * (i == j ? 0.5 : 1.0);
+        double pf, pc;
+        if (dv == 0.0) {
+            pf = 0.0;
+            pc = 1.0;
+        } else {
+            const double qv = vf / dv;
+            const double y = 1.5 * qv * qv;
+            pf = (1.0 + y) * exp(-y);
+            pc = y < kSeriesY
+                     ? y * y * (1.0 / 2.0 + y * (-1.0 / 3.0 + y * (1.0 / 8.0 + y * (-1.0 / 30.0 +
+                       y * (1.0 / 144.0 + y * (-1.0 / 840.0 + y * (1.0 / 5760.0)))))))
+                     : 1.0 - pf;
+        }
+        kc[p] = (OT)(K * pc);
+        kf[p] = (OT)(K * pf);
     }
 }
 
@@ -475,21 +529,36 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 hipError_t launch_build(int N, const double *m, const double *me, double eta, double chi,
                         int split, uint32_t *pij, uint32_t *dst, double *cw0, double *cw1,
                         double *rw0, double *rw1, double *fm, double *dE, double *invE,
-                        double *invdm, int *fcol, int *frow, hipStream_t st) {
+                        double *invdm, int *fcol, int *frow, int *cdiag, int *rdiag,
+                        hipStream_t st) {
     const int P = N * (N + 1) / 2;
     hipLaunchKernelGGL(k_build_pairs, dim3((P + 255) / 256), dim3(256), 0, st, N, m, me, chi,
                        split, pij, dst, cw0, cw1, rw0, rw1, fm);
     hipLaunchKernelGGL(k_build_frag, dim3((N + 255) / 256), dim3(256), 0, st, N, m, me, eta, chi,
-                       dE, invE, invdm, fcol, frow);
+                       dE, invE, invdm, fcol, frow, cdiag, rdiag);
+    return hipGetLastError();
+}
+
+template <typename OT>
+static hipError_t launch_rates_t(const Tables &T, long C, const CellArrays &cells,
+                                 const double *v_dust, const double *v_frag, OT *Kc, OT *Kf,
+                                 hipStream_t st) {
+    if (C == 0) return hipSuccess;
+    if (hipError_t e = allow_lds(k_rates<kBlock, OT>, lds_bytes(9 * T.N))) return e;
+    hipLaunchKernelGGL((k_rates<kBlock, OT>), dim3((unsigned)C), dim3(kBlock), lds_bytes(9 * T.N),
+                       st, T, cells, v_dust, v_frag, Kc, Kf);
     return hipGetLastError();
 }
 
 hipError_t launch_rates(const Tables &T, long C, const CellArrays &cells, const double *v_dust,
                         const double *v_frag, double *Kc, double *Kf, hipStream_t st) {
-    if (C == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rates<kBlock>, dim3((unsigned)C), dim3(kBlock), lds_bytes(4 * T.N), st, T,
-                       cells, v_dust, v_frag, Kc, Kf);
-    return hipGetLastError();
+    return launch_rates_t(T, C, cells, v_dust, v_frag, Kc, Kf, st);
+}
+
+hipError_t launch_rates_f32(const Tables &T, long C, const CellArrays &cells,
+                            const double *v_dust, const double *v_frag, float *Kc, float *Kf,
+                            hipStream_t st) {
+    return launch_rates_t(T, C, cells, v_dust, v_frag, Kc, Kf, st);
 }
 
 hipError_t launch_rhs(const Tables &T, long C, const double *rho, const double *Kc,

@@ -1,5 +1,5 @@
 // coag_launch.h -- argument blocks and launchers shared by the host API
-// (coag_api.hip) and the kernels (coag_kernels.hip, coag_split.hip).
+// (coag_api.hip) and the kernels (coag_kernels.hip, coag_step2.hip, coag_batch.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,9 +39,13 @@ struct AdjArgs {
 hipError_t launch_build(int N, const double *m, const double *me, double eta, double chi,
                         int split, uint32_t *pij, uint32_t *dst, double *cw0, double *cw1,
                         double *rw0, double *rw1, double *fm, double *dE, double *invE,
-                        double *invdm, int *fcol, int *frow, hipStream_t st);
+                        double *invdm, int *fcol, int *frow, int *cdiag, int *rdiag,
+                        hipStream_t st);
 hipError_t launch_rates(const Tables &T, long C, const CellArrays &cells, const double *v_dust,
                         const double *v_frag, double *Kc, double *Kf, hipStream_t st);
+hipError_t launch_rates_f32(const Tables &T, long C, const CellArrays &cells,
+                            const double *v_dust, const double *v_frag, float *Kc, float *Kf,
+                            hipStream_t st);
 hipError_t launch_rhs(const Tables &T, long C, const double *rho, const double *Kc,
                       const double *Kf, double *out, hipStream_t st);
 size_t step_lds_bytes(int N);

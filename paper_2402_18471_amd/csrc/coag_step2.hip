@@ -53,7 +53,7 @@ __device__ __forceinline__ int bin_le(const double *m, int N, double x) {
 // LDS view of the per-bin tables of one workgroup
 struct BinLds {
     const double *m, *idm, *dE, *invE;
-    const int *fcol, *frow;
+    const int *fcol, *frow, *cdiag, *rdiag;
 };
 
 // Per-wave schedule: a run of n slots starting at diagonal d0 of row block b0
@@ -79,6 +79,30 @@ __device__ __forceinline__ void next_slot(int N, int &b, int &d) {
 
 __device__ __forceinline__ int diag_base(int N, int d) { return d * N - (d * (d - 1)) / 2; }
 
+// Copy one cell's packed-triangle array from HBM into LDS in diagonal-major
+// order, kU loads in flight per thread before their stores.
+constexpr int kU = 8;
+__device__ __forceinline__ void scatter_diag(const Tables &T, const double *__restrict__ src,
+                                             double *dst) {
+    const int N = T.N, P = T.P;
+    for (int base = 0; base < P; base += kU * kBlock2) {
+        double v[kU];
+        uint32_t ij[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int p = base + u * kBlock2 + threadIdx.x;
+            v[u] = p < P ? src[p] : 0.0;
+            ij[u] = p < P ? T.pij[p] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int p = base + u * kBlock2 + threadIdx.x;
+            const int i = pair_i(ij[u]), j = pair_j(ij[u]);
+            if (p < P) dst[diag_base(N, i - j) + j] = v[u];
+        }
+    }
+}
+
 // Rates of the cell on chip.  HBM is read in packed-triangle order (thread t
 // takes pairs t, t + 512, ...: fully coalesced) and scattered into LDS in
 // diagonal-major order; Kc goes on from LDS into this lane's registers, Kf
@@ -90,11 +114,7 @@ __device__ __forceinline__ void load_rates(const Tables &T, const Run &r,
                                            double *kfl) {
     const int N = T.N, P = T.P;
     const int lane = threadIdx.x & 63;
-    for (int p = threadIdx.x; p < P; p += kBlock2) {
-        const uint32_t ij = T.pij[p];
-        const int i = pair_i(ij), j = pair_j(ij);
-        kfl[diag_base(N, i - j) + j] = Kc[p];
-    }
+    scatter_diag(T, Kc, kfl);
     __syncthreads();
     int b = r.b0, d = r.d0;
 #pragma clang loop unroll(full)
@@ -108,19 +128,38 @@ __device__ __forceinline__ void load_rates(const Tables &T, const Run &r,
         }
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < P; p += kBlock2) {
-        const uint32_t ij = T.pij[p];
-        const int i = pair_i(ij), j = pair_j(ij);
-        kfl[diag_base(N, i - j) + j] = Kf[p];
-    }
+    scatter_diag(T, Kf, kfl);
+    (void)P;
+}
+
+// Per-lane bracket keys of the first pair of this wave's run (row block b0,
+// diagonal d0), found once per kernel; later row blocks start at d = 0, whose
+// keys come from the per-bin tables cdiag / rdiag.
+struct Keys0 {
+    int kc, kr;
+};
+
+__device__ __forceinline__ Keys0 first_keys(const Tables &T, const BinLds &B, const Run &run) {
+    const int N = T.N, lane = threadIdx.x & 63;
+    const int hi = N - 64 * run.b0, lo = hi > 64 ? hi - 64 : 0;
+    const int i = lo + lane;
+    const int ic = i < hi ? i : 0;
+    const int j0 = ic - run.d0 >= 0 ? ic - run.d0 : 0;
+    const double mi = B.m[ic], mj = B.m[j0];
+    const double cm = T.chi * mj;
+    const double mr = cm < mi ? mi - cm : 0.0;
+    return Keys0{bin_le(B.m, N, mi + mj), mr >= B.m[0] ? bin_le(B.m, N, mr) : 0};
 }
 
 // Right-hand side of eq. `smol` for one cell from register-resident rates.
-//   y [N] (LDS) in, out [N] (LDS or global) out, w >= 5N doubles of LDS.
-template <int SLOTS>
+//   y [N] (LDS) in, out [N] (LDS or global) out, w >= 5N + 4 doubles of LDS.
+// The slot body is branch-free apart from the rare moves of the two
+// bracketing bins; lanes without a pair (masked) deposit exact zeros.
+template <int SLOTS, bool NUMBER>
 __device__ __forceinline__ void rhs_reg(const Tables &T, const BinLds &B, const Run &run,
-                        const double (&kc)[SLOTS], const double *kfl, const double *y,
-                        double *out, double *w) {
+                                        const Keys0 &k0, const double (&kc)[SLOTS],
+                                        const double *kfl, const double *y, double *out,
+                                        double *w) {
     const int N = T.N;
     // keep the per-row set-up below inside the sub-step loop (recomputing it is
     // cheaper than the registers it would hold across the whole loop)
@@ -135,7 +174,6 @@ __device__ __forceinline__ void rhs_reg(const Tables &T, const BinLds &B, const 
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const double chi = T.chi;
-    const bool number = T.split == 1;
     const double *m = B.m;
 
     int cur_b = -1, ic = 0;
@@ -147,115 +185,151 @@ __device__ __forceinline__ void rhs_reg(const Tables &T, const BinLds &B, const 
     double mrl = 0, mru = 0, idr = 0;
 
     auto flush_coag = [&]() {
-        if (aX != 0.0) atomicAdd(&gain[kcb], aX);
-        if (aY != 0.0) atomicAdd(&gain[kcb + 1], aY);
+        atomicAdd(&gain[kcb], aX);
+        atomicAdd(&gain[kcb + 1 < N ? kcb + 1 : kcb], aY);
         aX = 0.0;
         aY = 0.0;
     };
     auto flush_rem = [&]() {
-        if (aZ != 0.0) atomicAdd(&gain[krb], aZ);
-        if (aW != 0.0) atomicAdd(&gain[krb + 1], aW);
+        atomicAdd(&gain[krb], aZ);
+        atomicAdd(&gain[krb + 1 < N ? krb + 1 : krb], aW);
         aZ = 0.0;
         aW = 0.0;
     };
-    auto flush_row = [&]() {
-        flush_coag();
-        flush_rem();
-        if (accL != 0.0) atomicAdd(&loss[ic], mi * accL);
-        if (aF != 0.0) atomicAdd(&phi[B.frow[ic]], aF);
-        accL = 0.0;
-        aF = 0.0;
-    };
+    // the top bin keeps finite stand-ins for m[k+1] (its weights are selected away)
     auto set_coag = [&](int k) {
         kcb = k;
         mcl = m[k];
-        mcu = k + 1 < N ? m[k + 1] : INFINITY;
+        mcu = k + 1 < N ? m[k + 1] : 2.0 * mcl;
         idc = B.idm[k];
     };
     auto set_rem = [&](int k) {
         krb = k;
         mrl = m[k];
-        mru = k + 1 < N ? m[k + 1] : INFINITY;
+        mru = k + 1 < N ? m[k + 1] : 2.0 * mrl;
         idr = B.idm[k];
     };
 
+    struct Ops {
+        double nj, mj, kf;
+        int fj;
+    };
+    // operands of a slot that come from LDS, loaded one slot ahead so that
+    // their latency overlaps the previous slot's arithmetic and atomics
+    auto fetch = [&](int bb, int dd) -> Ops {
+        const int hi = N - 64 * bb, lo = hi > 64 ? hi - 64 : 0;
+        const int i = lo + lane, j = i - dd;
+        const int jc = (i < hi && j >= 0) ? j : 0;
+        return Ops{n[jc], m[jc], kfl[diag_base(N, dd) + jc], B.fcol[jc]};
+    };
     int b = run.b0, d = run.d0;
+    Ops cur = fetch(b, d);
 #pragma clang loop unroll(full)
     for (int t = 0; t < SLOTS; ++t) {
         if (t < run.n) {
             if (b != cur_b) {
-                if (cur_b >= 0) flush_row();
+                if (cur_b >= 0) {
+                    flush_coag();
+                    flush_rem();
+                    atomicAdd(&loss[ic], mi * accL);
+                    atomicAdd(&phi[B.frow[ic]], aF);
+                    accL = 0.0;
+                    aF = 0.0;
+                }
+                const bool first = cur_b < 0;
                 cur_b = b;
                 const int hi = N - 64 * b, lo = hi > 64 ? hi - 64 : 0;
                 const int i = lo + lane;
                 rowok = i < hi;
                 ic = rowok ? i : 0;
-                ni = rowok ? n[ic] : 0.0;
+                ni = n[ic];
                 mi = m[ic];
-                const int j0 = ic - d >= 0 ? ic - d : 0;
-                set_coag(bin_le(m, N, mi + m[j0]));
-                const double cm0 = chi * m[j0];
-                const double Mr0 = cm0 < mi ? mi - cm0 : 0.0;
-                set_rem(Mr0 >= m[0] ? bin_le(m, N, Mr0) : 0);
+                set_coag(first ? k0.kc : B.cdiag[ic]);
+                set_rem(first ? k0.kr : B.rdiag[ic]);
             }
             const int j = ic - d;
             const bool ok = rowok && j >= 0;
             const int jc = ok ? j : 0;
-            const double nj = n[jc], mj = m[jc];
+            const double nj = cur.nj, mj = cur.mj, kfv = cur.kf;
+            const int fj = cur.fj;
+            int b2 = b, d2 = d;
+            next_slot(N, b2, d2);
+            if (t + 1 < run.n) cur = fetch(b2, d2);
             const double a = ok ? ni * nj : 0.0;
-            const double rc = a * kc[t], rf = a * kfl[diag_base(N, d) + jc];
+            const double rc = a * kc[t], rf = a * kfv;
             const double sum = rc + rf;
             accL += sum;
-            if (ok) atomicAdd(&loss[jc], mj * sum);
-            // coagulation product m_i + m_j between bins kcb, kcb + 1
+            atomicAdd(&loss[jc], mj * sum);
+            // coagulation product m_i + m_j between bins kcb, kcb + 1 (all of it
+            // in the top bin when it is at or above m_{N-1})
             const double M = mi + mj;
             while (M < mcl && kcb > 0) {
                 flush_coag();
                 set_coag(kcb - 1);
             }
-            if (kcb == N - 1) {
-                aX += rc * M;
-            } else {
+            {
+                const bool top = kcb == N - 1;
                 const double eps = (mcu - M) * idc, ome = (M - mcl) * idc;
-                aX += rc * (number ? eps * mcl : eps * M);
-                aY += rc * (number ? ome * mcu : ome * M);
+                const double w0 = top ? M : (NUMBER ? eps * mcl : eps * M);
+                const double w1 = top ? 0.0 : (NUMBER ? ome * mcu : ome * M);
+                aX += rc * w0;
+                aY += rc * w1;
             }
-            // cratering remnant m_i - chi m_j between bins krb, krb + 1
+            // cratering remnant m_i - chi m_j between bins krb, krb + 1 (whole at
+            // the top bin, or in bin 0 below m_0; zero when the target is destroyed)
             const double cm = chi * mj;
             const bool crater = cm < mi;
             const double Mr = crater ? mi - cm : 0.0;
-            if (Mr > 0.0) {
-                while (Mr >= mru) {
-                    flush_rem();
-                    set_rem(krb + 1);
-                }
-                // at or above the top bin (m_i - chi m_j rounds to m_i when the
-                // impactor is light enough), or below bin 0: all into that bin
-                if (krb == N - 1 || Mr < mrl) {
-                    aZ += rf * Mr;
-                } else {
-                    const double eps = (mru - Mr) * idr, ome = (Mr - mrl) * idr;
-                    aZ += rf * (number ? eps * mrl : eps * Mr);
-                    aW += rf * (number ? ome * mru : ome * Mr);
-                }
+            while (Mr >= mru && krb < N - 1) {
+                flush_rem();
+                set_rem(krb + 1);
             }
-            // fragments: total mass minus remnant, collected by the top fragment bin
+            {
+                const bool whole = krb == N - 1 || Mr < mrl;
+                const double eps = (mru - Mr) * idr, ome = (Mr - mrl) * idr;
+                const double z0 = whole ? Mr : (NUMBER ? eps * mrl : eps * Mr);
+                const double z1 = whole ? 0.0 : (NUMBER ? ome * mru : ome * Mr);
+                aZ += rf * z0;
+                aW += rf * z1;
+            }
+            // fragments: total mass minus remnant, collected by the top fragment
+            // bin (set by chi m_j when cratering, by m_i when the target is destroyed)
             const double fr = rf * (M - Mr);
-            if (crater) {
-                if (ok) atomicAdd(&phi[B.fcol[jc]], fr);
-            } else {
-                aF += fr;
-            }
-            next_slot(N, b, d);
+            atomicAdd(&phi[fj], crater ? fr : 0.0);
+            aF += crater ? 0.0 : fr;
+            b = b2;
+            d = d2;
         }
     }
-    if (cur_b >= 0) flush_row();
+    if (cur_b >= 0) {
+        flush_coag();
+        flush_rem();
+        atomicAdd(&loss[ic], mi * accL);
+        atomicAdd(&phi[B.frow[ic]], aF);
+    }
     __syncthreads();
-    for (int k = threadIdx.x; k < N; k += kBlock2) phi[k] *= B.invE[k];
+    // fragments: S_k = sum_{l >= k} phi_l invE_l, each wave scanning 64 bins
+    // in parallel, then adding the totals of the chunks above it
+    const int wv = threadIdx.x >> 6, nch = (N + 63) >> 6;
+    double *tot = suf + N;                          // [nch] chunk totals (in w)
+    if (wv < nch) {
+        const int k = N - 1 - (64 * wv + lane);    // lane 0: top of the chunk
+        double v = k >= 0 ? phi[k] * B.invE[k] : 0.0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double u = __shfl_up(v, o, 64);
+            if (lane >= o) v += u;
+        }
+        if (k >= 0) suf[k] = v;
+        if (lane == 63) tot[wv] = v;
+    }
     __syncthreads();
-    wave0_suffix_sum(phi, suf, N);
-    __syncthreads();
-    for (int k = threadIdx.x; k < N; k += kBlock2) out[k] = (gain[k] + B.dE[k] * suf[k]) - loss[k];
+    for (int k = threadIdx.x; k < N; k += kBlock2) {
+        const int ch = (N - 1 - k) >> 6;
+        double above = 0.0;
+        for (int q = 0; q < ch; ++q) above += tot[q];
+        out[k] = (gain[k] + B.dE[k] * (suf[k] + above)) - loss[k];
+    }
     __syncthreads();
 }
 
@@ -269,7 +343,8 @@ struct Lds2 {
 __device__ __forceinline__ Lds2 load_tables(const Tables &T, double *lds) {
     const int N = T.N;
     double *m = lds, *idm = lds + N, *dE = lds + 2 * N, *invE = lds + 3 * N;
-    int *fcol = (int *)(lds + 4 * N), *frow = fcol + N;
+    int *fcol = (int *)(lds + 4 * N), *frow = fcol + N, *cdiag = fcol + 2 * N,
+        *rdiag = fcol + 3 * N;
     for (int k = threadIdx.x; k < N; k += kBlock2) {
         m[k] = T.m[k];
         idm[k] = T.invdm[k];
@@ -277,15 +352,17 @@ __device__ __forceinline__ Lds2 load_tables(const Tables &T, double *lds) {
         invE[k] = T.invE[k];
         fcol[k] = T.fcol[k];
         frow[k] = T.frow[k];
+        cdiag[k] = T.cdiag[k];
+        rdiag[k] = T.rdiag[k];
     }
     Lds2 L;
-    L.B = BinLds{m, idm, dE, invE, fcol, frow};
-    L.kf = lds + 5 * N;
-    L.tail = lds + 5 * N + T.P;
+    L.B = BinLds{m, idm, dE, invE, fcol, frow, cdiag, rdiag};
+    L.kf = lds + 6 * N;
+    L.tail = lds + 6 * N + T.P;
     return L;
 }
 
-template <int SLOTS>
+template <int SLOTS, bool NUMBER>
 __global__ __launch_bounds__(kBlock2) void k_rhs2(Tables T, const double *__restrict__ rho,
                                                   const double *__restrict__ Kc,
                                                   const double *__restrict__ Kf,
@@ -301,7 +378,8 @@ __global__ __launch_bounds__(kBlock2) void k_rhs2(Tables T, const double *__rest
     load_rates<SLOTS>(T, run, Kc + c * P, Kf + c * P, kc, L.kf);
     for (int k = threadIdx.x; k < N; k += kBlock2) y[k] = rho[c * N + k];
     __syncthreads();
-    rhs_reg<SLOTS>(T, L.B, run, kc, L.kf, y, f, w);
+    const Keys0 k0 = first_keys(T, L.B, run);
+    rhs_reg<SLOTS, NUMBER>(T, L.B, run, k0, kc, L.kf, y, f, w);
     for (int k = threadIdx.x; k < N; k += kBlock2) out[c * N + k] = f[k];
 }
 
@@ -311,7 +389,7 @@ __global__ __launch_bounds__(kBlock2) void k_rhs2(Tables T, const double *__rest
 //   0: k1 = f(y)           (entry)
 //   2: k2 = f(y + h/2 k1)   3: k3 = f(y + 3h/4 k2)
 //   4: k4 = f(y+)           (y+ = y + h (2/9 k1 + 1/3 k2 + 4/9 k3))
-template <int SLOTS>
+template <int SLOTS, bool NUMBER>
 __global__ __launch_bounds__(kBlock2) void k_step2(Tables T, StepArgs a) {
     extern __shared__ double lds[];
     const long c = blockIdx.x;
@@ -330,6 +408,7 @@ __global__ __launch_bounds__(kBlock2) void k_step2(Tables T, StepArgs a) {
         msum += y[k];
     }
     const double mass0 = block_reduce<kBlock2, 0>(msum, red);   // also orders the Kf stores
+    const Keys0 k0 = first_keys(T, L.B, run);
     const bool adaptive = a.mode == 0;
     const double dt = a.dt;
     const double atol = a.atol_rel * mass0;
@@ -365,7 +444,7 @@ __global__ __launch_bounds__(kBlock2) void k_step2(Tables T, StepArgs a) {
     while (true) {
         const double *xin = stage == 0 ? y : stage == 4 ? yn : ys;
         double *kout = stage == 0 ? k1 : stage == 2 ? k2 : stage == 3 ? k3 : k4;
-        rhs_reg<SLOTS>(T, L.B, run, kc, L.kf, xin, kout, w);
+        rhs_reg<SLOTS, NUMBER>(T, L.B, run, k0, kc, L.kf, xin, kout, w);
         if (stage == 0 || stage == 4) {
             if (stage == 4) {
                 bool accept = true;
@@ -455,10 +534,10 @@ static hipError_t allow_lds2(K kernel, size_t bytes) {
 }
 
 static size_t rhs2_lds_bytes(int N) {
-    return (size_t)(5 * N + N * (N + 1) / 2 + 7 * N) * sizeof(double);
+    return (size_t)(6 * N + N * (N + 1) / 2 + 7 * N + 8) * sizeof(double);
 }
 static size_t step2_lds_bytes(int N) {
-    return (size_t)(5 * N + N * (N + 1) / 2 + 12 * N + 64) * sizeof(double);
+    return (size_t)(6 * N + N * (N + 1) / 2 + 12 * N + 72) * sizeof(double);
 }
 constexpr size_t kLdsBytes = 160 * 1024;
 
@@ -485,9 +564,15 @@ hipError_t launch_rhs2(const Tables &T, long C, const double *rho, const double 
     switch (pick_slots(T.N)) {
 #define CASE(s)                                                                              \
     case s:                                                                                  \
-        if (hipError_t e = allow_lds2(k_rhs2<s>, bytes)) return e;                          \
-        hipLaunchKernelGGL(k_rhs2<s>, dim3((unsigned)C), dim3(kBlock2), bytes, st, T, rho, Kc, \
-                           Kf, out);                                                         \
+        if (T.split == 1) {                                                                  \
+            if (hipError_t e = allow_lds2(k_rhs2<s, true>, bytes)) return e;                \
+            hipLaunchKernelGGL((k_rhs2<s, true>), dim3((unsigned)C), dim3(kBlock2), bytes, st, \
+                               T, rho, Kc, Kf, out);                                         \
+        } else {                                                                             \
+            if (hipError_t e = allow_lds2(k_rhs2<s, false>, bytes)) return e;               \
+            hipLaunchKernelGGL((k_rhs2<s, false>), dim3((unsigned)C), dim3(kBlock2), bytes, \
+                               st, T, rho, Kc, Kf, out);                                     \
+        }                                                                                    \
         break;
         COAG_SLOT_CASES(CASE)
 #undef CASE
@@ -502,8 +587,15 @@ hipError_t launch_step2(const Tables &T, long C, const StepArgs &a, hipStream_t 
     switch (pick_slots(T.N)) {
 #define CASE(s)                                                                              \
     case s:                                                                                  \
-        if (hipError_t e = allow_lds2(k_step2<s>, bytes)) return e;                         \
-        hipLaunchKernelGGL(k_step2<s>, dim3((unsigned)C), dim3(kBlock2), bytes, st, T, a);  \
+        if (T.split == 1) {                                                                  \
+            if (hipError_t e = allow_lds2(k_step2<s, true>, bytes)) return e;               \
+            hipLaunchKernelGGL((k_step2<s, true>), dim3((unsigned)C), dim3(kBlock2), bytes, \
+                               st, T, a);                                                    \
+        } else {                                                                             \
+            if (hipError_t e = allow_lds2(k_step2<s, false>, bytes)) return e;              \
+            hipLaunchKernelGGL((k_step2<s, false>), dim3((unsigned)C), dim3(kBlock2), bytes, \
+                               st, T, a);                                                    \
+        }                                                                                    \
         break;
         COAG_SLOT_CASES(CASE)
 #undef CASE

@@ -17,7 +17,8 @@ def test_library_exports_every_declared_symbol(L):
     lib = L.load()
     names = L.header_symbols()
     assert set(names) == {"coag_mass_grid", "coag_create", "coag_destroy", "coag_last_error",
-                          "coag_rates", "coag_rhs", "coag_step", "coag_step_backward"}
+                          "coag_rates", "coag_rates_f32", "coag_rhs", "coag_step",
+                          "coag_step_backward"}
     for n in names:
         assert hasattr(lib, n), n
 
@@ -74,7 +75,7 @@ def test_create_rejects_bad_grids_on_host(L):
 
 def test_calls_reject_null_context(L):
     lib = L.load()
-    tol = L.Tol(1e-2, 1e-10, 0.0, 10, 0, 0, 0)
+    tol = L.Tol(1e-2, 1e-10, 0.0, 10, 0, 0, 0, 0)
     assert lib.coag_rhs(None, 1, None, None, None, None, None) == L.COAG_EINVAL
     assert lib.coag_step(None, 1, None, None, None, 1.0, None, ct.byref(tol), None, None, None,
                          None, None) == L.COAG_EINVAL

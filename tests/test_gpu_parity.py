@@ -25,6 +25,8 @@ gross terms that make them up:
                input is rounded differently.
   adjoint      |dg| <= 1e-9 max|g| on a well-conditioned grid
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -43,16 +45,32 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def _case(O, cfg_name, n_r, n_z, n_bins=None, seed_cells=None):
+def make_ctx(m, me, s, kernel=None, **kw):
+    """A context whose FP64 steps take the given kernel ("batch": 16 cells per
+    workgroup on the matrix cores, "cell": one workgroup per cell)."""
+    from paper_2402_18471_amd.coag import coag_create
+    old = os.environ.get("COAG_STEP_KERNEL")
+    if kernel is not None:
+        os.environ["COAG_STEP_KERNEL"] = kernel
+    try:
+        return coag_create(m, me, s, **kw)
+    finally:
+        if old is None:
+            os.environ.pop("COAG_STEP_KERNEL", None)
+        else:
+            os.environ["COAG_STEP_KERNEL"] = old
+
+
+def _case(O, cfg_name, n_r, n_z, n_bins=None, seed_cells=None, kernel=None):
     from paper_2402_18471_amd import disc
-    from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
+    from paper_2402_18471_amd.coag import coag_mass_grid
     cfg = disc.CONFIGS[cfg_name]
     if (n_r, n_z) != (cfg.n_r, cfg.n_z) or n_bins is not None:
         cfg = disc.scaled(cfg, n_r, n_z, n_bins)
     m, me, s = coag_mass_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
     g = O.make_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
     d = disc.make_disc(cfg, g.s)
-    ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
+    ctx = make_ctx(m, me, s, kernel, rho_m=cfg.rho_m)
     cells_t = {k: _t(v) for k, v in d["cells"].items()}
     return cfg, g, d, ctx, cells_t
 
@@ -130,10 +148,15 @@ def _gl_dt(O, g, rho0, Kc, Kf, dt):
     return dt * (gain + loss)
 
 
+KERNELS = ["batch", "cell"]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("case", [("disc64x32_n100", 8, 4, None),
-                                  ("disc256x128_n150", 4, 2, None)])
-def test_step_fixed_parity(O, case):
-    cfg, g, d, ctx, cells = _case(O, *case)
+                                  ("disc256x128_n150", 4, 2, None),
+                                  ("disc64x32_n100", 5, 7, None)])
+def test_step_fixed_parity(O, case, kernel):
+    cfg, g, d, ctx, cells = _case(O, *case, kernel=kernel)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
     C = d["rho"].shape[0]
     # the populated-everywhere start takes shorter steps: with a full dt and three
@@ -152,15 +175,16 @@ def test_step_fixed_parity(O, case):
         np.testing.assert_array_equal(_np(r["h_log"])[:, :n], o["h_log"][:, :n])
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("case", [("disc64x32_n100", 16, 8, None),
                                   ("disc256x128_n150", 8, 4, None),
                                   ("disc512x256_n200", 4, 2, None)])
-def test_step_adaptive_parity_by_replay(O, case):
+def test_step_adaptive_parity_by_replay(O, case, kernel):
     """ADAPTIVE on the GPU, then the oracle replays the GPU's accepted steps:
     states agree per bin; the accept/reject counts agree with the oracle's
     own adaptive run in nearly every cell (rounding can flip a borderline
     decision)."""
-    cfg, g, d, ctx, cells = _case(O, *case)
+    cfg, g, d, ctx, cells = _case(O, *case, kernel=kernel)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
     rho0 = d["rho"]
     dt = d["dt"] * 20
@@ -182,8 +206,9 @@ def test_step_adaptive_parity_by_replay(O, case):
     assert np.max(np.abs(m1 / m0 - 1)) < 1e-13
 
 
-def test_step_renorm_and_status(O):
-    cfg, g, d, ctx, cells = _case(O, "disc64x32_n100", 4, 2, None)
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_step_renorm_and_status(O, kernel):
+    cfg, g, d, ctx, cells = _case(O, "disc64x32_n100", 4, 2, None, kernel=kernel)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
     rho0 = d["rho"].copy()
     rho0[1, 5] = np.nan
