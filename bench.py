@@ -7,11 +7,23 @@ from step to step.  The metric is accepted cell-steps per second, a
 cell-step being one accepted BS3 sub-step of one cell (three right-hand-side
 evaluations, error estimate and FP64 update).
 
-Prints one JSON line (see the design doc for every field).
+Measured on the 256x128-cell, 150-bin disc:
+  value          FP64 path (batched FP64 matrix-core step)
+  split_bf16     split-BF16 step with FP32 rates: throughput, speedup over the
+                 FP64 path, and its per-bin error against the FP64 GPU path
+                 (replaying the same steps) on a stratified sample of cells
+  adjoint        coag_step_backward time over forward (rates + step) time on
+                 the 64x32-cell, 100-bin disc
+  roofline       the FP64 step kernel against HBM bandwidth: algorithmic
+                 bytes = (16 P + 16 N) per cell per right-hand side
+  cpu_baseline   the CPU oracle on a sample of the same workload
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as ct
 import json
 import os
 import sys
@@ -23,23 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector, dense
-HBM_PEAK_GBS = 8000.0
-
-
-def rhs_flops(N: int) -> float:
-    """Algorithmic FP64 operations of one cell right-hand side: per pair 3 to
-    form the coagulating/fragmenting collision rates, 10 for the five sparse
-    gain deposits (coag pair, remnant pair, fragment bin), 4 for the two
-    partners' losses; per bin 8 (n = rho/m, fragment suffix sum and the final
-    gain - loss)."""
-    P = N * (N + 1) // 2
-    return 17.0 * P + 8.0 * N
-
-
-def step_algebra_flops(N: int) -> float:
-    """Stage states, update and error estimate of one BS3 attempt per cell."""
-    return 20.0 * N
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 
 
 def parse():
@@ -49,10 +45,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="disc256x128_n150")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-sample-cells", type=int, default=512)
-    ap.add_argument("--prec", choices=("fp64", "split"), default="fp64")
-    ap.add_argument("--rates", choices=("f64", "f32"), default="f64")
-    ap.add_argument("--kernel", choices=("batch", "cell"), default="batch")
+    ap.add_argument("--kernel", choices=("batch", "cell"), default="batch",
+                    help="FP64 step kernel (cell: one workgroup per cell)")
     return ap.parse_args()
 
 
@@ -82,6 +79,147 @@ def cpu_baseline(cfg, disc_mod, n_cells, target_s=10.0, max_calls=2000):
                       f"calls each (rates + adaptive step), {acc} accepted cell-steps in {dt:.1f} s"}
 
 
+class Disc:
+    """A synthetic disc resident on the GPU with its context and buffers."""
+
+    def __init__(self, cfg_name, torch, kernel="batch"):
+        from paper_2402_18471_amd import disc
+        from paper_2402_18471_amd import _lib as L
+        from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
+        if kernel == "cell":
+            os.environ["COAG_STEP_KERNEL"] = "cell"
+        self.torch, self.L = torch, L
+        self.cfg = cfg = disc.CONFIGS[cfg_name]
+        dev = self.dev = "cuda:0"
+        m, me, s = coag_mass_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
+        self.d = d = disc.make_disc(cfg, s)
+        self.C, self.N = cfg.n_cells, cfg.n_bins
+        self.t = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt,
+                                                              device=dev)
+        self.ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
+        os.environ.pop("COAG_STEP_KERNEL", None)
+        self.P = self.ctx.P
+        self.cells = {k: self.t(v) for k, v in d["cells"].items()}
+        self.v_dust, self.v_frag = self.t(d["v_dust"]), self.t(d["v_frag"])
+        self.lib = L.load()
+        self.cs = L.Cells(*[self.cells[k].data_ptr() for k in
+                            ("T", "rho_g", "c_s", "Omega", "H", "nu_mol", "alpha")])
+        self.stream = torch.cuda.current_stream()
+        self.sp = ct.c_void_p(self.stream.cuda_stream)
+
+    def p(self, x):
+        return ct.c_void_p(x.data_ptr()) if x is not None else None
+
+    def forward(self, steps, warmup, split, rho=None):
+        """steps + warmup coagulation calls from rho (default: the initial
+        state); per-call HIP-event times of rates and step on the stream."""
+        torch, L = self.torch, self.L
+        C = self.C
+        f32 = split
+        rho = (self.t(self.d["rho"]) if rho is None else rho.clone())
+        h = torch.zeros(C, dtype=torch.float64, device=self.dev)
+        n = warmup + steps
+        nsub = torch.zeros((n, C), dtype=torch.int32, device=self.dev)
+        nrej = torch.zeros((n, C), dtype=torch.int32, device=self.dev)
+        status = torch.zeros(C, dtype=torch.int32, device=self.dev)
+        max_sub = 4096
+        Kc = torch.empty((C, self.P), dtype=torch.float32 if f32 else torch.float64, device=self.dev)
+        Kf = torch.empty_like(Kc)
+        tol = L.Tol(1e-2, 1e-10, 1e-12, max_sub, L.ADAPTIVE,
+                    L.PREC_SPLIT_BF16 if split else L.PREC_FP64, 0, 1 if f32 else 0)
+        rates_fn = self.lib.coag_rates_f32 if f32 else self.lib.coag_rates
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n)]
+        p, sp, h_ = self.p, self.sp, self.ctx._h
+        dt = float(self.d["dt"])
+
+        def one(i):
+            e = ev[i]
+            e[0].record(self.stream)
+            L.check(rates_fn(h_, C, ct.byref(self.cs), p(self.v_dust), p(self.v_frag), p(Kc), p(Kf),
+                             sp), h_)
+            e[1].record(self.stream)
+            L.check(self.lib.coag_step(h_, C, p(rho), p(Kc), p(Kf), dt, p(h), ct.byref(tol),
+                                       p(nsub[i]), p(nrej[i]), None, p(status), sp), h_)
+            e[2].record(self.stream)
+
+        for i in range(warmup):
+            one(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(warmup, n):
+            one(i)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sl = slice(warmup, n)
+        ns = nsub[sl].cpu().numpy().astype(np.int64)
+        nr = nrej[sl].cpu().numpy().astype(np.int64)
+        return dict(wall=wall, acc=int(ns.sum()), rej=int(nr.sum()), ns=ns, nr=nr,
+                    rates_ms=np.array([ev[i][0].elapsed_time(ev[i][1]) for i in range(warmup, n)]),
+                    step_ms=np.array([ev[i][1].elapsed_time(ev[i][2]) for i in range(warmup, n)]),
+                    failed=int((status.cpu().numpy() != 0).sum()), rho=rho)
+
+
+def split_error(D, rho_start, sample):
+    """Split-BF16 step against the FP64 GPU step over the same steps, on a
+    sample of cells: FP64 ADAPTIVE call over 20 dt, then the split step
+    replays its accepted steps.  Resolved bins hold >= 1e-12 of the cell's
+    mass; the rest are reported relative to the cell's mass."""
+    torch, L = D.torch, D.L
+    from paper_2402_18471_amd import disc
+    idx = np.asarray(sample)
+    sub = disc.subset_cells(D.d, idx)
+    cells = {k: D.t(v) for k, v in sub["cells"].items()}
+    vd, vf = D.t(sub["v_dust"]), D.t(sub["v_frag"])
+    rho0 = rho_start[D.t(idx, torch.int64)].contiguous()
+    dt = 20.0 * float(D.d["dt"])
+    K64 = D.ctx.coag_rates(cells, vd, vf)
+    K32 = D.ctx.coag_rates_f32(cells, vd, vf)
+    a = D.ctx.coag_step(rho0.clone(), *K64, dt, max_sub=512)
+    b = D.ctx.coag_step(rho0.clone(), *K32, dt, mode=L.REPLAY, prec=L.PREC_SPLIT_BF16,
+                        nsub=a["nsub"].clone(), h_log=a["h_log"])
+    torch.cuda.synchronize()
+    x, ref = b["rho"].cpu().numpy(), a["rho"].cpu().numpy()
+    M = ref.sum(1, keepdims=True)
+    res = ref >= 1e-12 * M
+    err = np.abs(x - ref)
+    return {"sample": f"{len(idx)} cells (every {D.C // len(idx)}th), state after the FP64 timed "
+                      f"calls, one call over 20 dt; split replays the FP64 path's steps",
+            "max_rel_err_resolved_bins": float(np.max(err[res] / ref[res])),
+            "max_abs_err_unresolved_bins_over_cell_mass": float(np.max((err / M)[~res]))
+            if np.any(~res) else 0.0,
+            "max_total_mass_err": float(np.max(np.abs(x.sum(1) / rho0.cpu().numpy().sum(1) - 1))),
+            "status_ok": bool(np.all(b["status"].cpu().numpy() == 0))}
+
+
+def adjoint_ratio(torch, calls=3):
+    """coag_step_backward time / forward (rates + step) time, per call, on the
+    64x32 x 100 adjoint disc (HIP events on the stream)."""
+    D = Disc("disc64x32_n100_adj", torch)
+    f = D.forward(calls, 1, False)
+    # the first call from the initial state, its steps recorded, is the one differentiated
+    rho_in = D.t(D.d["rho"])
+    Kc, Kf = D.ctx.coag_rates(D.cells, D.v_dust, D.v_frag)
+    a = D.ctx.coag_step(rho_in.clone(), Kc, Kf, float(D.d["dt"]), max_sub=64)
+    nsub, hlog = a["nsub"], a["h_log"]
+    g_out = torch.ones((D.C, D.N), dtype=torch.float64, device=D.dev) / rho_in.sum(1, keepdim=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    D.ctx.coag_step_backward(rho_in, D.cells, D.v_dust, D.v_frag, hlog, nsub, g_out)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(calls):
+        ev[0].record(D.stream)
+        D.ctx.coag_step_backward(rho_in, D.cells, D.v_dust, D.v_frag, hlog, nsub, g_out)
+        ev[1].record(D.stream)
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    fwd = float(np.mean(f["rates_ms"] + f["step_ms"]))
+    return {"workload": D.cfg.name, "backward_ms": float(np.mean(ms)), "forward_ms": fwd,
+            "adjoint_over_forward": float(np.mean(ms)) / fwd,
+            "note": "backward of the first call from the initial state (recomputes rates and "
+                    "stage states); forward = rates + ADAPTIVE step per call; accepted sub-steps "
+                    f"per cell in the differentiated call {float(nsub.float().mean()):.2f}"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -90,99 +228,55 @@ def main():
         sys.exit(2)
     import torch
     from paper_2402_18471_amd import disc
-    from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
 
-    cfg = disc.CONFIGS[args.config]
-    dev = "cuda:0"
-    if args.kernel == "cell":
-        os.environ["COAG_STEP_KERNEL"] = "cell"
-    split = args.prec == "split"
-    f32 = args.rates == "f32"
-    if f32 and not split:
-        sys.exit("--rates f32 needs --prec split")
-    m, me, s = coag_mass_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
-    d = disc.make_disc(cfg, s)
-    C, N = cfg.n_cells, cfg.n_bins
-    t = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
-    ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
-    cells = {k: t(v) for k, v in d["cells"].items()}
-    v_dust, v_frag = t(d["v_dust"]), t(d["v_frag"])
-    rho = t(d["rho"])
-    h = torch.zeros(C, dtype=torch.float64, device=dev)
-    K = args.steps
-    nsub_all = torch.zeros((args.warmup + K, C), dtype=torch.int32, device=dev)
-    nrej_all = torch.zeros((args.warmup + K, C), dtype=torch.int32, device=dev)
-    status = torch.zeros(C, dtype=torch.int32, device=dev)
-    Kc = torch.empty((C, ctx.P), dtype=torch.float32 if f32 else torch.float64, device=dev)
-    Kf = torch.empty_like(Kc)
-    from paper_2402_18471_amd import _lib as L
-    import ctypes as ct
-    lib = L.load()
-    tol = L.Tol(1e-2, 1e-10, 1e-12, 4096, L.ADAPTIVE,
-                L.PREC_SPLIT_BF16 if split else L.PREC_FP64, 0, 1 if f32 else 0)
-    rates_fn = lib.coag_rates_f32 if f32 else lib.coag_rates
-    cs = L.Cells(*[cells[k].data_ptr() for k in ("T", "rho_g", "c_s", "Omega", "H", "nu_mol", "alpha")])
-    stream = torch.cuda.current_stream()
-    sp = ct.c_void_p(stream.cuda_stream)
-    p = lambda x: ct.c_void_p(x.data_ptr())
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(args.warmup + K)]
-
-    def one(i):
-        e0, e1, e2 = ev[i]
-        e0.record(stream)
-        L.check(rates_fn(ctx._h, C, ct.byref(cs), p(v_dust), p(v_frag), p(Kc), p(Kf), sp), ctx._h)
-        e1.record(stream)
-        L.check(lib.coag_step(ctx._h, C, p(rho), p(Kc), p(Kf), float(d["dt"]), p(h), ct.byref(tol),
-                              p(nsub_all[i]), p(nrej_all[i]), None, p(status), sp), ctx._h)
-        e2.record(stream)
-
-    for i in range(args.warmup):
-        one(i)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.warmup, args.warmup + K):
-        one(i)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    st = status.cpu().numpy()
-    ns = nsub_all[args.warmup:].cpu().numpy().astype(np.int64)
-    nr = nrej_all[args.warmup:].cpu().numpy().astype(np.int64)
-    acc, rej = int(ns.sum()), int(nr.sum())
-    rates_ms = np.array([ev[i][0].elapsed_time(ev[i][1]) for i in range(args.warmup, args.warmup + K)])
-    step_ms = np.array([ev[i][1].elapsed_time(ev[i][2]) for i in range(args.warmup, args.warmup + K)])
-    # dominant kernel: the step kernel; algorithmic FP64 work per launch
-    attempts_per_step = (ns + nr).sum(axis=1)          # per launch, summed over cells
-    calls_per_launch = C                                # one k1 evaluation per cell per call
-    flops = (3.0 * attempts_per_step + calls_per_launch) * rhs_flops(N) + \
-        attempts_per_step * step_algebra_flops(N)
-    achieved_tf = float(np.mean(flops / (step_ms * 1e-3)) / 1e12)
+    D = Disc(args.config, torch, args.kernel)
+    C, N, P = D.C, D.N, D.P
+    K, W = args.steps, args.warmup
+    f = D.forward(K, W, False)
+    attempts = f["ns"] + f["nr"]                              # [steps][C]
+    rhs_per_launch = (3 * attempts + 1).sum(axis=1)            # k1 once per cell per call
+    bytes_per_launch = rhs_per_launch * (16.0 * P + 16.0 * N)
+    achieved = float(np.mean(bytes_per_launch / (f["step_ms"] * 1e-3)) / 1e9)
     out = {
-        "metric": "coag cell-steps/s (accepted BS3 sub-steps x cells per second), FP64",
-        "value": acc / wall,
+        "metric": "coag cell-steps/s, FP64 vs split-BF16 at <=1e-6 rel err; adjoint/fwd time",
+        "value": f["acc"] / f["wall"],
         "unit": "cell-steps/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": wall / K * 1e3,
+        "warmup": W,
+        "ms_per_step": f["wall"] / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded transition-disc gas state, drift/settling velocities, MRN start)",
-        "config": {"workload": cfg.name, "cells": C, "bins": N, "pairs": ctx.P,
-                   "dt_yr": cfg.dt / 3.15576e7, "rtol": 1e-2, "atol_rel": 1e-10},
-        "attempted_cell_steps_per_s": (acc + rej) / wall,
-        "cells_calls_per_s": C * K / wall,
-        "rates_ms": float(rates_ms.mean()),
-        "step_ms": float(step_ms.mean()),
-        "cells_failed": int((st != 0).sum()),
-        "roofline": {"bound": "alu", "kernel": "k_step (coag_step, FP64)",
-                     "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": None},
+        "config": {"workload": D.cfg.name, "cells": C, "bins": N, "pairs": P,
+                   "dt_yr": D.cfg.dt / 3.15576e7, "rtol": 1e-2, "atol_rel": 1e-10,
+                   "fp64_step_kernel": args.kernel},
+        "attempted_cell_steps_per_s": (f["acc"] + f["rej"]) / f["wall"],
+        "cells_calls_per_s": C * K / f["wall"],
+        "rates_ms": float(f["rates_ms"].mean()),
+        "step_ms": float(f["step_ms"].mean()),
+        "cells_failed": f["failed"],
+        "roofline": {"bound": "hbm", "kernel": "coag_step FP64 (k_step_batch)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes": "(16 P + 16 N) B per cell per right-hand side; "
+                                          "1 + 3 x attempts right-hand sides per cell per call"},
     }
+    if not args.no_split:
+        s = D.forward(K, W, True)
+        out["split_bf16"] = {
+            "value": s["acc"] / s["wall"], "unit": "cell-steps/s", "rates": "f32",
+            "ms_per_step": s["wall"] / K * 1e3, "rates_ms": float(s["rates_ms"].mean()),
+            "step_ms": float(s["step_ms"].mean()), "cells_failed": s["failed"],
+            "speedup_vs_fp64": (s["acc"] / s["wall"]) / (f["acc"] / f["wall"]),
+            "error_vs_fp64": split_error(D, f["rho"], np.arange(0, C, max(1, C // 512))),
+        }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_ratio(torch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, disc, args.cpu_sample_cells)
+        out["cpu_baseline"] = cpu_baseline(D.cfg, disc, args.cpu_sample_cells)
     print(json.dumps(out), flush=True)
 
 

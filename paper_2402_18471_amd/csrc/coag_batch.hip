@@ -7,9 +7,10 @@
 // fixed redistribution tensor of eqs. `Cijk`, `Rijk`) is a matrix product
 // with the cells as its M dimension.  Pairs are taken in chunks of 16 of one
 // row i (K = 32: the coagulating and the fragmenting rate of each pair); all
-// coagulation and remnant products of row i, and the loss m_i of the heavier
-// grain, land in a 16-bin window, the N dimension.  D is stored per chunk as
-// MFMA B operands (FP64, or three BF16 limbs).
+// coagulation and remnant products of row i land in a 16-bin window, the N
+// dimension, together with bin i, which loses m_i per collision.  D, with that
+// loss folded into its entries, is stored per chunk as MFMA B operands (FP64,
+// or three BF16 limbs).
 //
 // What is not a matrix product stays on the vector units in FP64: the loss of
 // the lighter grain m_j (a column sum), the fragment mass deposited at the top
@@ -19,8 +20,8 @@
 // Split-BF16 form: the chunk operand A = n_j K / max_k n_k is rounded to FP32
 // and split into three BF16 limbs a0 + a1 + a2 (each the rounding of what the
 // previous ones leave), D likewise; the six limb products of order <= 2 are
-// accumulated in FP32 by v_mfma_f32_16x16x32_bf16 and scaled back
-// (x n_i max_k n_k) into the FP64 accumulators when the row changes.  The
+// accumulated in FP32 by v_mfma_f32_16x16x32_bf16 over one chunk and scaled
+// back (x n_i max_k n_k) into the FP64 accumulators after every chunk.  The
 // total mass of each cell is restored in FP64 at the end of the call.
 //
 // Cells of a batch that have finished (or lie past C) contribute zero rates
@@ -67,7 +68,10 @@ int n_chunks(int N) {
 }
 
 // D entry of pair (i, j), kind (0 coagulation, 1 fragmentation), bin: the mass
-// put into the bin per unit rate minus m_i for bin i (the heavier grain's loss)
+// put into the bin per unit rate minus m_i for bin i (the heavier grain's
+// loss).  Folding the loss into the entry keeps the near-cancellation of a
+// heavy grain sweeping up a light one (gain into bin i ~ m_i) exact in FP64
+// before any rounding to limbs.
 __device__ double d_entry(const Tables &T, int i, int j, int kind, int bin) {
     if (j > i) return 0.0;
     const long p = (long)i * (i + 1) / 2 + j;
@@ -163,10 +167,12 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
     const int N = T.N;
     const long P = T.P;
     const long cell0 = (long)blockIdx.x * kBC;
-    double *nv = lds, *net = lds + kBC * N, *phi = lds + 2 * kBC * N;
-    Ctl *ctl = (Ctl *)(lds + 3 * kBC * N);
+    double *nv = lds, *net = lds + kBC * N, *phi = lds + 2 * kBC * N, *mk = lds + 3 * kBC * N;
+    Ctl *ctl = (Ctl *)(mk + N);
     int *flag = (int *)(ctl + kBC);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int k = threadIdx.x; k < N; k += kBBlock) mk[k] = T.m[k];
     const bool adaptive = a.mode == 0;
     const double dt = a.dt;
     // workspace of cell c: k1, k2, k3, k4, yn, each [N]
@@ -230,7 +236,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                         x = y[k] + hh * (2.0 / 9.0 * k1[k] + 1.0 / 3.0 * k2[k] + 4.0 / 9.0 * k3[k]);
                         yn[k] = x;
                     }
-                    const double n = x / T.m[k];
+                    const double n = x / mk[k];
                     nv[c * N + k] = n;
                     mx = fmax(mx, fabs(n));
                 }
@@ -252,23 +258,36 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
     };
 
     // gain and loss of all 16 cells into net (gain - loss without the
-    // fragment distribution) and phi (fragment mass per top bin)
+    // fragment distribution) and phi (fragment mass per top bin).  Each wave
+    // takes a contiguous range of chunks; the operands of the next chunk are
+    // loaded while the current one is processed.
     auto contract = [&]() {
         const int cl = lane & 15, g = lane >> 4;
         const long cb = cell0 + cl < C ? cell0 + cl : C - 1;
         const int NC = B.NC;
         const int c0 = (int)((long)wv * NC / kBWaves), c1 = (int)((long)(wv + 1) * NC / kBWaves);
+        if (c0 >= c1) return;
         const double *nrow = nv + cl * N;
         double *netc = net + cl * N, *phic = phi + cl * N;
         const double inv_nmax = PREC == 1 ? ctl[cl].inv_nmax : 0.0;
-        int cur = -1;
+        // chunks follow each other row by row: (i, q) -> (i, q + 1) or (i + 1, 0)
+        auto advance = [](int &i, int &q) {
+            if (16 * (q + 1) <= i) ++q;
+            else { ++i; q = 0; }
+        };
+        const int cr0 = __builtin_amdgcn_readfirstlane(B.crow[c0]);
+        int ci = cr0 & 0xffff, cq = cr0 >> 16;
+        int cur = ci;
         f64x4 acc64 = {0.0, 0.0, 0.0, 0.0};
         f32x4 acc32 = {0.0f, 0.0f, 0.0f, 0.0f};
+        // accumulator layouts (lane l, register r -> row, column = l % 16):
+        //   v_mfma_f64_16x16x4f64      row l / 16 + 4 r
+        //   v_mfma_f32_16x16x32_bf16   row 4 (l / 16) + r
         auto flush = [&](int i) {
             const int bin = B.wb[i] + cl;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int c = 4 * g + r;
+                const int c = PREC == 0 ? g + 4 * r : 4 * g + r;
                 if (PREC == 0) {
                     atomicAdd(&net[c * N + bin], acc64[r]);
                 } else {
@@ -277,43 +296,101 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                 }
             }
         };
-        for (int ch = c0; ch < c1; ++ch) {
-            const int cr = B.crow[ch];
-            const int i = cr & 0xffff, q = cr >> 16;
-            if (i != cur) {
-                if (cur >= 0) flush(cur);
-                cur = i;
-                acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
-                acc32 = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            }
-            const long prow = (long)i * (i + 1) / 2;
-            const double ni = nrow[i];
-            if (PREC == 0) {
-                const RT *Kc = (const RT *)a.Kc + cb * P, *Kf = (const RT *)a.Kf + cb * P;
+        if (PREC == 0) {
+            // lane (cell, g): pairs 16q + 4g + s, s = 0..3, both kinds
+            struct Ops {
+                double kc[4], kf[4], fm[4], b[8];
+                uint32_t dst[4];
+            };
+            const RT *Kc = (const RT *)a.Kc + cb * P, *Kf = (const RT *)a.Kf + cb * P;
+            auto fetch = [&](int ch, int i, int q, Ops &o) {
+                const long prow = (long)i * (i + 1) / 2;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int j = 16 * q + 4 * g + s;
+                    const long p = prow + (j <= i ? j : i);
+                    o.kc[s] = (double)Kc[p];
+                    o.kf[s] = (double)Kf[p];
+                    o.dst[s] = T.dst[p];
+                    o.fm[s] = T.fm[p];
+                }
+                const double *bt = B.b64 + (long)ch * 8 * 64 + lane;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) o.b[s] = bt[s * 64];
+            };
+            Ops o;
+            fetch(c0, ci, cq, o);
+            for (int ch = c0; ch < c1; ++ch) {
+                const int i = ci, q = cq;
+                advance(ci, cq);
+                Ops nx;
+                if (ch + 1 < c1) fetch(ch + 1, ci, cq, nx);
+                if (i != cur) {
+                    flush(cur);
+                    cur = i;
+                    acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
+                }
+                const double ni = nrow[i];
                 double rc[4], rf[4];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const int j = 16 * q + 4 * g + s;
                     const bool ok = j <= i;
                     const int jc = ok ? j : i;
-                    const long p = prow + jc;
                     const double nn = ok ? ni * nrow[jc] : 0.0;
-                    rc[s] = nn * (double)Kc[p];
-                    rf[s] = nn * (double)Kf[p];
-                    atomicAdd(&netc[jc], -T.m[jc] * (rc[s] + rf[s]));
-                    atomicAdd(&phic[T.dst[p] >> 20], T.fm[p] * rf[s]);
+                    rc[s] = nn * o.kc[s];
+                    rf[s] = nn * o.kf[s];
+                    atomicAdd(&netc[jc], -mk[jc] * (rc[s] + rf[s]));
+                    atomicAdd(&phic[o.dst[s] >> 20], o.fm[s] * rf[s]);
                 }
-                const double *bt = B.b64 + (long)ch * 8 * 64 + lane;
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
-                    acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rc[s], bt[s * 64], acc64, 0, 0, 0);
+                    acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rc[s], o.b[s], acc64, 0, 0, 0);
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
-                    acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rf[s], bt[(4 + s) * 64], acc64, 0,
-                                                                 0, 0);
-            } else {
-                const int kind = g >> 1;
-                const RT *K = (const RT *)(kind ? a.Kf : a.Kc) + cb * P;
+                    acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rf[s], o.b[4 + s], acc64, 0, 0, 0);
+                if (ch + 1 < c1) o = nx;
+            }
+        } else {
+            // lane (cell, g): pairs 16q + 8 (g % 2) + e, e = 0..7, kind g / 2
+            const int kind = g >> 1;
+            struct Ops {
+                RT k[8];
+                double fm[8];
+                uint32_t dst[8];
+                uint4 b0, b1, b2;
+            };
+            const RT *K = (const RT *)(kind ? a.Kf : a.Kc) + cb * P;
+            auto fetch = [&](int ch, int i, int q, Ops &o) {
+                const long prow = (long)i * (i + 1) / 2;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int j = 16 * q + 8 * (g & 1) + e;
+                    const long p = prow + (j <= i ? j : i);
+                    o.k[e] = K[p];
+                    if (kind) {
+                        o.dst[e] = T.dst[p];
+                        o.fm[e] = T.fm[p];
+                    }
+                }
+                const uint4 *bt = B.b16 + (long)ch * 3 * 64 + lane;
+                o.b0 = bt[0];
+                o.b1 = bt[64];
+                o.b2 = bt[128];
+            };
+            Ops o;
+            fetch(c0, ci, cq, o);
+            for (int ch = c0; ch < c1; ++ch) {
+                const int i = ci, q = cq;
+                advance(ci, cq);
+                Ops nx;
+                if (ch + 1 < c1) fetch(ch + 1, ci, cq, nx);
+                if (ch > c0) {                 // one chunk per FP32 accumulation
+                    flush(cur);
+                    acc32 = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                }
+                cur = i;
+                const double ni = nrow[i];
                 union {
                     __bf16 h[8];
                     bf16x8 v;
@@ -323,33 +400,32 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                     const int j = 16 * q + 8 * (g & 1) + e;
                     const bool ok = j <= i;
                     const int jc = ok ? j : i;
-                    const long p = prow + jc;
-                    const double t = ok ? nrow[jc] * (double)K[p] : 0.0;
+                    const double t = ok ? nrow[jc] * (double)o.k[e] : 0.0;
                     const double r = ni * t;
-                    atomicAdd(&netc[jc], -T.m[jc] * r);
-                    if (kind) atomicAdd(&phic[T.dst[p] >> 20], T.fm[p] * r);
+                    atomicAdd(&netc[jc], -mk[jc] * r);
+                    if (kind) atomicAdd(&phic[o.dst[e] >> 20], o.fm[e] * r);
                     const Limbs L = split3((float)(t * inv_nmax));
                     A0.h[e] = L.a0;
                     A1.h[e] = L.a1;
                     A2.h[e] = L.a2;
                 }
-                const uint4 *bt = B.b16 + (long)ch * 3 * 64 + lane;
                 union {
                     uint4 u;
                     bf16x8 v;
                 } B0, B1, B2;
-                B0.u = bt[0];
-                B1.u = bt[64];
-                B2.u = bt[128];
+                B0.u = o.b0;
+                B1.u = o.b1;
+                B2.u = o.b2;
                 acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0.v, B0.v, acc32, 0, 0, 0);
                 acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0.v, B1.v, acc32, 0, 0, 0);
                 acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1.v, B0.v, acc32, 0, 0, 0);
                 acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0.v, B2.v, acc32, 0, 0, 0);
                 acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1.v, B1.v, acc32, 0, 0, 0);
                 acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2.v, B0.v, acc32, 0, 0, 0);
+                if (ch + 1 < c1) o = nx;
             }
         }
-        if (cur >= 0) flush(cur);
+        flush(cur);
     };
 
     // slope of cell c: net + dE_k sum_{l >= k} phi_l invE_l, into ws slot v
@@ -512,7 +588,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
 }
 
 size_t batch_lds_bytes(int N) {
-    return (size_t)3 * kBC * N * sizeof(double) + kBC * sizeof(Ctl) + 64;
+    return (size_t)(3 * kBC + 1) * N * sizeof(double) + kBC * sizeof(Ctl) + 64;
 }
 
 template <typename K>

@@ -35,7 +35,8 @@ struct Tables {
     const int *fcol;       // [N] top fragment bin when the largest fragment is chi m_j
     const int *frow;       // [N] top fragment bin when the largest fragment is m_i
     const int *cdiag;      // [N] lower bracketing bin of the product m_i + m_i
-    const int *rdiag;      // [N] lower bracketing bin of the remnant m_i - chi m_i (0 if none)
+    const int *rdiag;      // [N] lower bracketing bin of the remnant of the first cratering
+                           //     pair (i, j) of row i, the largest such j (0 if none)
     double chi;            // excavated mass / impactor mass
     int split;             // 0 MASS, 1 NUMBER
 };

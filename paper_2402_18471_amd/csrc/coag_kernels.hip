@@ -118,8 +118,12 @@ __global__ void k_build_frag(int N, const double *__restrict__ m, const double *
         return lo;
     };
     cdiag[k] = below(m[k] + m[k]);
-    const double cm = chi * m[k];
-    const double mr = cm < m[k] ? m[k] - cm : 0.0;
+    // remnant bracket of the first cratering pair of row k (largest j <= k with
+    // chi m_j < m_k): the remnant grows as j falls, so every later pair of the
+    // row lies at or above it; 0 if the row has none or it is below m_0
+    int jr = k;
+    while (jr >= 0 && !(chi * m[jr] < m[k])) --jr;
+    const double mr = jr >= 0 ? m[k] - chi * m[jr] : 0.0;
     rdiag[k] = mr >= m[0] ? below(mr) : 0;
 }
 

@@ -147,7 +147,9 @@ __device__ __forceinline__ Keys0 first_keys(const Tables &T, const BinLds &B, co
     const int j0 = ic - run.d0 >= 0 ? ic - run.d0 : 0;
     const double mi = B.m[ic], mj = B.m[j0];
     const double cm = T.chi * mj;
-    const double mr = cm < mi ? mi - cm : 0.0;
+    // a destroyed target (no remnant) starts from the row's first cratering bracket
+    if (!(cm < mi)) return Keys0{bin_le(B.m, N, mi + mj), B.rdiag[ic]};
+    const double mr = mi - cm;
     return Keys0{bin_le(B.m, N, mi + mj), mr >= B.m[0] ? bin_le(B.m, N, mr) : 0};
 }
 
