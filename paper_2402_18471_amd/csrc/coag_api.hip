@@ -313,7 +313,7 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void 
     a.h_log = h_log;
     const bool split = tol->prec == COAG_PREC_SPLIT_BF16;
     if (split || (ctx->batch_fp64 && batch_available(ctx->T, ctx->B))) {
-        if (int r = ensure_ws(ctx, batch_ws_bytes(ctx->N, C))) return r;
+        if (int r = ensure_ws(ctx, batch_ws_bytes(ctx->N, C, split ? 1 : 0))) return r;
         HIP_TRY(ctx, launch_step_batch(ctx->T, ctx->B, C, a, split ? 1 : 0, tol->rates_f32,
                                        (double *)ctx->ws, (hipStream_t)stream));
     } else if (reg_path_available(ctx->N)) {

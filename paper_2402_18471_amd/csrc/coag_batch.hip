@@ -17,7 +17,7 @@
 // fragment bin (the accumulation of Rafikov et al. 2020, eq. `Nijk`), the
 // fragment suffix sum, stage states, error control and the update.
 //
-// Split-BF16 form: the chunk operand A = n_j K / max_k n_k is rounded to FP32
+// Split-BF16 form: the chunk operand A = n_j K / max_k n_k is formed in FP32
 // and split into three BF16 limbs a0 + a1 + a2 (each the rounding of what the
 // previous ones leave), D likewise; the six limb products of order <= 2 are
 // accumulated in FP32 by v_mfma_f32_16x16x32_bf16 over one chunk and scaled
@@ -57,6 +57,42 @@ __device__ __forceinline__ Limbs split3(float x) {
     L.a2 = (__bf16)r2;
     return L;
 }
+
+// the same for eight values, as the BF16x8 operands of one MFMA, two values
+// per conversion instruction
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+struct Limbs8 {
+    bf16x8 a0, a1, a2;
+};
+__device__ __forceinline__ Limbs8 split3x8(const float (&x)[8]) {
+    union {
+        bf16x2 h[4];
+        bf16x8 v;
+    } A0, A1, A2;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const f32x2 v = {x[2 * e], x[2 * e + 1]};
+        A0.h[e] = __builtin_convertvector(v, bf16x2);
+        const f32x2 r1 = v - __builtin_convertvector(A0.h[e], f32x2);
+        A1.h[e] = __builtin_convertvector(r1, bf16x2);
+        const f32x2 r2 = r1 - __builtin_convertvector(A1.h[e], f32x2);
+        A2.h[e] = __builtin_convertvector(r2, bf16x2);
+    }
+    return Limbs8{A0.v, A1.v, A2.v};
+}
+
+// mass of the fragments of pair (i, j), total minus remnant (eq. `fragrem`),
+// evaluated exactly as the pair tables are: no contraction into an FMA
+__device__ __forceinline__ double frag_mass(double mi, double mj, double chi, bool &crater) {
+#pragma clang fp contract(off)
+    const double cm = chi * mj;
+    crater = cm < mi;
+    const double mrem = crater ? mi - cm : 0.0;
+    return (mi + mj) - mrem;
+}
+
+constexpr int kRing = 2;     // chunks of rates in flight per wave
 
 // ---------------------------------------------------------------------------
 // tables
@@ -162,21 +198,55 @@ __device__ __forceinline__ double wave_min_d(double v) {
 
 template <int PREC, typename RT>
 __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B, StepArgs a,
-                                                        long C, double *ws) {
+                                                        long C, double *ws, RT *wk) {
     extern __shared__ double lds[];
     const int N = T.N;
     const long P = T.P;
     const long cell0 = (long)blockIdx.x * kBC;
     double *nv = lds, *net = lds + kBC * N, *phi = lds + 2 * kBC * N, *mk = lds + 3 * kBC * N;
-    Ctl *ctl = (Ctl *)(mk + N);
+    int *fcol = (int *)(mk + N), *frow = fcol + N;
+    float *nf = (float *)(frow + N);              // split form: [16][N] n_k / max_k n_k
+    Ctl *ctl = (Ctl *)(lds + (3 * kBC + 2 + kBC / 2) * N);
     int *flag = (int *)(ctl + kBC);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int k = threadIdx.x; k < N; k += kBBlock) mk[k] = T.m[k];
+    for (int k = threadIdx.x; k < N; k += kBBlock) {
+        mk[k] = T.m[k];
+        fcol[k] = T.fcol[k];
+        frow[k] = T.frow[k];
+    }
     const bool adaptive = a.mode == 0;
     const double dt = a.dt;
     // workspace of cell c: k1, k2, k3, k4, yn, each [N]
     auto wsp = [&](int c, int v) { return ws + ((cell0 + c) * 5 + v) * (long)N; };
+
+    // ---- FP64 form: the batch's rates, reordered once per call: pair-major,
+    // then kind (Kc, Kf), then the 16 cells, so that every right-hand side
+    // streams whole cache lines (rows of [C][P] are P elements apart).  Staged
+    // through LDS tiles of TP pairs (rows padded by one element against bank
+    // conflicts).  The split form, bound by its vector work rather than by the
+    // rate stream, reads [C][P] directly.
+    RT *const kb = wk + (long)blockIdx.x * P * 2 * kBC;
+    if (PREC == 0) {
+        RT *tile = (RT *)lds;
+        const int cap = (int)((3 * kBC * N * sizeof(double)) / (2 * kBC * sizeof(RT))) - 1;
+        const int TP = cap < 128 ? cap : 128, TS = TP + 1;
+        const RT *src[2] = {(const RT *)a.Kc, (const RT *)a.Kf};
+        for (long p0 = 0; p0 < P; p0 += TP) {
+            const int np = P - p0 < TP ? (int)(P - p0) : TP;
+            for (int t = threadIdx.x; t < 2 * kBC * TP; t += kBBlock) {
+                const int pp = t % TP, r = t / TP;          // r = kind * 16 + cell
+                const long gc = cell0 + (r & 15);
+                tile[r * TS + pp] = (pp < np && gc < C) ? src[r >> 4][gc * P + p0 + pp] : (RT)0;
+            }
+            __syncthreads();
+            for (int t = threadIdx.x; t < 2 * kBC * np; t += kBBlock) {
+                const int r = t & 31, pp = t >> 5;          // r = kind * 16 + cell
+                kb[(p0 + pp) * 2 * kBC + r] = tile[r * TS + pp];
+            }
+            __syncthreads();
+        }
+    }
 
     // ---- set-up: each wave owns cells wv and wv + 8 ----
     for (int u = 0; u < 2; ++u) {
@@ -249,9 +319,11 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             }
             if (PREC == 1) {
                 mx = wave_max_d(mx);
+                const double inv = mx > 0.0 ? 1.0 / mx : 0.0;
+                for (int k = lane; k < N; k += 64) nf[c * N + k] = (float)(nv[c * N + k] * inv);
                 if (lane == 0) {
                     ctl[c].nmax = mx;
-                    ctl[c].inv_nmax = mx > 0.0 ? 1.0 / mx : 0.0;
+                    ctl[c].inv_nmax = inv;
                 }
             }
         }
@@ -259,24 +331,27 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
 
     // gain and loss of all 16 cells into net (gain - loss without the
     // fragment distribution) and phi (fragment mass per top bin).  Each wave
-    // takes a contiguous range of chunks; the operands of the next chunk are
-    // loaded while the current one is processed.
+    // takes a contiguous range of chunks.  The rates, the one stream from HBM,
+    // are loaded kRing chunks ahead into a register ring, the D operands one
+    // chunk ahead.
     auto contract = [&]() {
         const int cl = lane & 15, g = lane >> 4;
-        const long cb = cell0 + cl < C ? cell0 + cl : C - 1;
         const int NC = B.NC;
         const int c0 = (int)((long)wv * NC / kBWaves), c1 = (int)((long)(wv + 1) * NC / kBWaves);
         if (c0 >= c1) return;
         const double *nrow = nv + cl * N;
         double *netc = net + cl * N, *phic = phi + cl * N;
-        const double inv_nmax = PREC == 1 ? ctl[cl].inv_nmax : 0.0;
+        const double nmax = PREC == 1 ? ctl[cl].nmax : 0.0;
+        const float *nfr = nf + cl * N;
+        const double chi = T.chi;
         // chunks follow each other row by row: (i, q) -> (i, q + 1) or (i + 1, 0)
         auto advance = [](int &i, int &q) {
             if (16 * (q + 1) <= i) ++q;
             else { ++i; q = 0; }
         };
         const int cr0 = __builtin_amdgcn_readfirstlane(B.crow[c0]);
-        int ci = cr0 & 0xffff, cq = cr0 >> 16;
+        int ci = cr0 & 0xffff, cq = cr0 >> 16;     // chunk being processed
+        int ri = ci, rq = cq;                       // next chunk to load rates for
         int cur = ci;
         f64x4 acc64 = {0.0, 0.0, 0.0, 0.0};
         f32x4 acc32 = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -296,133 +371,158 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                 }
             }
         };
+        // loss of the lighter grain and fragment deposit of one pair, FP64
+        auto column = [&](int i, int jc, double rsum, double rf, bool frag) {
+            atomicAdd(&netc[jc], -mk[jc] * rsum);
+            if (frag) {
+                bool crater;
+                const double fm = frag_mass(mk[i], mk[jc], chi, crater);
+                atomicAdd(&phic[crater ? fcol[jc] : frow[i]], fm * rf);
+            }
+        };
         if (PREC == 0) {
             // lane (cell, g): pairs 16q + 4g + s, s = 0..3, both kinds
-            struct Ops {
-                double kc[4], kf[4], fm[4], b[8];
-                uint32_t dst[4];
-            };
-            const RT *Kc = (const RT *)a.Kc + cb * P, *Kf = (const RT *)a.Kf + cb * P;
-            auto fetch = [&](int ch, int i, int q, Ops &o) {
+            double rkc[kRing][4], rkf[kRing][4], bb[2][8];
+            auto load_k = [&](int i, int q, double (&kc)[4], double (&kf)[4]) {
                 const long prow = (long)i * (i + 1) / 2;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const int j = 16 * q + 4 * g + s;
-                    const long p = prow + (j <= i ? j : i);
-                    o.kc[s] = (double)Kc[p];
-                    o.kf[s] = (double)Kf[p];
-                    o.dst[s] = T.dst[p];
-                    o.fm[s] = T.fm[p];
+                    const RT *kp = kb + (prow + (j <= i ? j : i)) * 2 * kBC + cl;
+                    kc[s] = (double)kp[0];
+                    kf[s] = (double)kp[kBC];
                 }
+            };
+            auto load_b = [&](int ch, double (&b)[8]) {
                 const double *bt = B.b64 + (long)ch * 8 * 64 + lane;
 #pragma unroll
-                for (int s = 0; s < 8; ++s) o.b[s] = bt[s * 64];
+                for (int s = 0; s < 8; ++s) b[s] = bt[s * 64];
             };
-            Ops o;
-            fetch(c0, ci, cq, o);
-            for (int ch = c0; ch < c1; ++ch) {
-                const int i = ci, q = cq;
-                advance(ci, cq);
-                Ops nx;
-                if (ch + 1 < c1) fetch(ch + 1, ci, cq, nx);
-                if (i != cur) {
-                    flush(cur);
-                    cur = i;
-                    acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int u = 0; u < kRing; ++u)
+                if (c0 + u < c1) {
+                    load_k(ri, rq, rkc[u], rkf[u]);
+                    advance(ri, rq);
                 }
-                const double ni = nrow[i];
-                double rc[4], rf[4];
+            load_b(c0, bb[0]);
+            for (int base = c0; base < c1; base += kRing) {
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int j = 16 * q + 4 * g + s;
-                    const bool ok = j <= i;
-                    const int jc = ok ? j : i;
-                    const double nn = ok ? ni * nrow[jc] : 0.0;
-                    rc[s] = nn * o.kc[s];
-                    rf[s] = nn * o.kf[s];
-                    atomicAdd(&netc[jc], -mk[jc] * (rc[s] + rf[s]));
-                    atomicAdd(&phic[o.dst[s] >> 20], o.fm[s] * rf[s]);
+                for (int u = 0; u < kRing; ++u) {
+                    const int ch = base + u;
+                    if (ch < c1) {
+                        const int i = ci, q = cq;
+                        advance(ci, cq);
+                        if (ch + 1 < c1) load_b(ch + 1, bb[(u + 1) & 1]);
+                        if (i != cur) {
+                            flush(cur);
+                            cur = i;
+                            acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
+                        }
+                        const double ni = nrow[i];
+                        double rc[4], rf[4];
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const int j = 16 * q + 4 * g + s;
+                            const bool ok = j <= i;
+                            const int jc = ok ? j : i;
+                            const double nn = ok ? ni * nrow[jc] : 0.0;
+                            rc[s] = nn * rkc[u][s];
+                            rf[s] = nn * rkf[u][s];
+                            column(i, jc, rc[s] + rf[s], rf[s], true);
+                        }
+                        const double(&b)[8] = bb[u & 1];
+#pragma unroll
+                        for (int s = 0; s < 4; ++s)
+                            acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rc[s], b[s], acc64, 0, 0, 0);
+#pragma unroll
+                        for (int s = 0; s < 4; ++s)
+                            acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rf[s], b[4 + s], acc64, 0,
+                                                                         0, 0);
+                        if (ch + kRing < c1) {
+                            load_k(ri, rq, rkc[u], rkf[u]);
+                            advance(ri, rq);
+                        }
+                    }
                 }
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rc[s], o.b[s], acc64, 0, 0, 0);
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rf[s], o.b[4 + s], acc64, 0, 0, 0);
-                if (ch + 1 < c1) o = nx;
             }
         } else {
             // lane (cell, g): pairs 16q + 8 (g % 2) + e, e = 0..7, kind g / 2
             const int kind = g >> 1;
-            struct Ops {
-                RT k[8];
-                double fm[8];
-                uint32_t dst[8];
-                uint4 b0, b1, b2;
-            };
+            const long cb = cell0 + cl < C ? cell0 + cl : C - 1;
             const RT *K = (const RT *)(kind ? a.Kf : a.Kc) + cb * P;
-            auto fetch = [&](int ch, int i, int q, Ops &o) {
+            RT rk[kRing][8];
+            uint4 bb[2][3];
+            auto load_k = [&](int i, int q, RT (&k)[8]) {
                 const long prow = (long)i * (i + 1) / 2;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int j = 16 * q + 8 * (g & 1) + e;
-                    const long p = prow + (j <= i ? j : i);
-                    o.k[e] = K[p];
-                    if (kind) {
-                        o.dst[e] = T.dst[p];
-                        o.fm[e] = T.fm[p];
+                    k[e] = K[prow + (j <= i ? j : i)];
+                }
+            };
+            auto load_b = [&](int ch, uint4 (&b)[3]) {
+                const uint4 *bt = B.b16 + (long)ch * 3 * 64 + lane;
+                b[0] = bt[0];
+                b[1] = bt[64];
+                b[2] = bt[128];
+            };
+#pragma unroll
+            for (int u = 0; u < kRing; ++u)
+                if (c0 + u < c1) {
+                    load_k(ri, rq, rk[u]);
+                    advance(ri, rq);
+                }
+            load_b(c0, bb[0]);
+            for (int base = c0; base < c1; base += kRing) {
+#pragma unroll
+                for (int u = 0; u < kRing; ++u) {
+                    const int ch = base + u;
+                    if (ch < c1) {
+                        const int i = ci, q = cq;
+                        advance(ci, cq);
+                        if (ch + 1 < c1) load_b(ch + 1, bb[(u + 1) & 1]);
+                        if (ch > c0) {             // one chunk per FP32 accumulation
+                            flush(cur);
+                            acc32 = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                        }
+                        cur = i;
+                        // x = n_j K / max n (FP32, the MFMA operand); the FP64
+                        // rate of the pair for the column terms is (n_i max n) x
+                        const double c64 = nrow[i] * nmax;
+                        float x[8];
+                        auto pairs = [&](bool full) {
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) {
+                                const int j = 16 * q + 8 * (g & 1) + e;
+                                const int jc = full ? j : (j <= i ? j : i);
+                                const float xe = nfr[jc] * (float)rk[u][e];
+                                x[e] = full || j <= i ? xe : 0.0f;
+                                const double r = c64 * (double)x[e];
+                                column(i, jc, r, r, kind != 0);
+                            }
+                        };
+                        if (16 * q + 15 <= i) pairs(true);
+                        else pairs(false);
+                        const Limbs8 L = split3x8(x);
+                        union {
+                            uint4 u;
+                            bf16x8 v;
+                        } B0, B1, B2;
+                        B0.u = bb[u & 1][0];
+                        B1.u = bb[u & 1][1];
+                        B2.u = bb[u & 1][2];
+                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B0.v, acc32, 0, 0, 0);
+                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B1.v, acc32, 0, 0, 0);
+                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B0.v, acc32, 0, 0, 0);
+                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B2.v, acc32, 0, 0, 0);
+                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B1.v, acc32, 0, 0, 0);
+                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a2, B0.v, acc32, 0, 0, 0);
+                        if (ch + kRing < c1) {
+                            load_k(ri, rq, rk[u]);
+                            advance(ri, rq);
+                        }
                     }
                 }
-                const uint4 *bt = B.b16 + (long)ch * 3 * 64 + lane;
-                o.b0 = bt[0];
-                o.b1 = bt[64];
-                o.b2 = bt[128];
-            };
-            Ops o;
-            fetch(c0, ci, cq, o);
-            for (int ch = c0; ch < c1; ++ch) {
-                const int i = ci, q = cq;
-                advance(ci, cq);
-                Ops nx;
-                if (ch + 1 < c1) fetch(ch + 1, ci, cq, nx);
-                if (ch > c0) {                 // one chunk per FP32 accumulation
-                    flush(cur);
-                    acc32 = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-                }
-                cur = i;
-                const double ni = nrow[i];
-                union {
-                    __bf16 h[8];
-                    bf16x8 v;
-                } A0, A1, A2;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int j = 16 * q + 8 * (g & 1) + e;
-                    const bool ok = j <= i;
-                    const int jc = ok ? j : i;
-                    const double t = ok ? nrow[jc] * (double)o.k[e] : 0.0;
-                    const double r = ni * t;
-                    atomicAdd(&netc[jc], -mk[jc] * r);
-                    if (kind) atomicAdd(&phic[o.dst[e] >> 20], o.fm[e] * r);
-                    const Limbs L = split3((float)(t * inv_nmax));
-                    A0.h[e] = L.a0;
-                    A1.h[e] = L.a1;
-                    A2.h[e] = L.a2;
-                }
-                union {
-                    uint4 u;
-                    bf16x8 v;
-                } B0, B1, B2;
-                B0.u = o.b0;
-                B1.u = o.b1;
-                B2.u = o.b2;
-                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0.v, B0.v, acc32, 0, 0, 0);
-                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0.v, B1.v, acc32, 0, 0, 0);
-                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1.v, B0.v, acc32, 0, 0, 0);
-                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0.v, B2.v, acc32, 0, 0, 0);
-                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1.v, B1.v, acc32, 0, 0, 0);
-                acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2.v, B0.v, acc32, 0, 0, 0);
-                if (ch + 1 < c1) o = nx;
             }
         }
         flush(cur);
@@ -588,7 +688,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
 }
 
 size_t batch_lds_bytes(int N) {
-    return (size_t)(3 * kBC + 1) * N * sizeof(double) + kBC * sizeof(Ctl) + 64;
+    return (size_t)(3 * kBC + 2 + kBC / 2) * N * sizeof(double) + kBC * sizeof(Ctl) + 64;
 }
 
 template <typename K>
@@ -650,9 +750,15 @@ bool batch_available(const Tables &T, const BatchTables &B) {
     return B.ok && batch_lds_bytes(T.N) <= 160 * 1024;
 }
 
-size_t batch_ws_bytes(int N, long C) {
+static size_t slope_bytes(int N, long C) {
     const long nb = (C + kBC - 1) / kBC;
-    return (size_t)nb * kBC * 5 * N * sizeof(double);
+    return ((size_t)nb * kBC * 5 * N * sizeof(double) + 255) & ~size_t(255);
+}
+
+size_t batch_ws_bytes(int N, long C, int prec) {
+    const long nb = (C + kBC - 1) / kBC;
+    const size_t P = (size_t)N * (N + 1) / 2;
+    return slope_bytes(N, C) + (prec == 0 ? (size_t)nb * P * 2 * kBC * sizeof(double) : 0);
 }
 
 hipError_t launch_step_batch(const Tables &T, const BatchTables &B, long C, const StepArgs &a,
@@ -664,7 +770,8 @@ hipError_t launch_step_batch(const Tables &T, const BatchTables &B, long C, cons
 #define LAUNCH(PR, RT)                                                                       \
     do {                                                                                     \
         if (hipError_t e = allow_lds_b(k_step_batch<PR, RT>, bytes)) return e;              \
-        hipLaunchKernelGGL((k_step_batch<PR, RT>), grid, block, bytes, st, T, B, a, C, ws); \
+        hipLaunchKernelGGL((k_step_batch<PR, RT>), grid, block, bytes, st, T, B, a, C, ws,  \
+                           (RT *)((char *)ws + slope_bytes(T.N, C)));                        \
     } while (0)
     if (prec == 0) {
         if (rates_f32) return hipErrorNotSupported;
