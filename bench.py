@@ -36,6 +36,27 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+KERNEL_SRC = os.path.join(ROOT, "paper_2402_18471_amd", "csrc", "coag_batch.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "k_step_batch_counters.json")
+
+
+def profiled_traffic(rhs_per_launch, kind):
+    """HBM bytes per launch of the batched step kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, calibrated on a
+    device copy of known size, per cell right-hand side), or None when there
+    is none or the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if c.get("kernel_source_sha256") != sha or kind not in c:
+        return None
+    per = c[kind]["fetch_bytes_per_cell_rhs"] + c[kind]["write_bytes_per_cell_rhs"]
+    return float(np.mean(rhs_per_launch) * per / 1e9)
 
 
 def parse():
@@ -50,6 +71,8 @@ def parse():
     ap.add_argument("--cpu-sample-cells", type=int, default=512)
     ap.add_argument("--kernel", choices=("batch", "cell"), default="batch",
                     help="FP64 step kernel (cell: one workgroup per cell)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with one 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -258,15 +281,28 @@ def main():
         "rates_ms": float(f["rates_ms"].mean()),
         "step_ms": float(f["step_ms"].mean()),
         "cells_failed": f["failed"],
+        "rhs_per_call": float(np.mean(rhs_per_launch)),
         "roofline": {"bound": "hbm", "kernel": "coag_step FP64 (k_step_batch)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic(rhs_per_launch, "fp64"),
+                     "traffic_unit": "GB per launch",
                      "algorithmic_bytes": "(16 P + 16 N) B per cell per right-hand side; "
                                           "1 + 3 x attempts right-hand sides per cell per call"},
     }
     if not args.no_split:
         s = D.forward(K, W, True)
+        s_rhs = (3 * (s["ns"] + s["nr"]) + 1).sum(axis=1)
+        s_alg = s_rhs * (8.0 * P + 16.0 * N)          # FP32 rates
+        s_ach = float(np.mean(s_alg / (s["step_ms"] * 1e-3)) / 1e9)
         out["split_bf16"] = {
+            "rhs_per_call": float(np.mean(s_rhs)),
+            "roofline": {"bound": "hbm", "kernel": "coag_step split-BF16 (k_step_batch)",
+                         "achieved": s_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": s_ach / HBM_PEAK_GBS,
+                         "traffic": profiled_traffic(s_rhs, "split"),
+                         "traffic_unit": "GB per launch",
+                         "algorithmic_bytes": "(8 P + 16 N) B per cell per right-hand side"},
             "value": s["acc"] / s["wall"], "unit": "cell-steps/s", "rates": "f32",
             "ms_per_step": s["wall"] / K * 1e3, "rates_ms": float(s["rates_ms"].mean()),
             "step_ms": float(s["step_ms"].mean()), "cells_failed": s["failed"],
@@ -277,6 +313,12 @@ def main():
         out["adjoint"] = adjoint_ratio(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(D.cfg, disc, args.cpu_sample_cells)
+    if args.calibrate_copy:
+        x = torch.ones(1 << 27, dtype=torch.float64, device=D.dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 1 << 30
     print(json.dumps(out), flush=True)
 
 
