@@ -11,17 +11,19 @@
 namespace coag {
 
 // Chunk tables of the batched contraction, built once per context.
-//   chunk c = (row i, column block q): the pairs (i, j), j in [16q, 16q + 16),
-//   j <= i; NC chunks in row-major order.  Every product of row i (coagulation
-//   and remnant targets, and bin i itself, which loses m_i per collision)
-//   lies in the 16-bin window [wb[i], wb[i] + 16).
-//   b64: FP64 B operands of v_mfma_f64_16x16x4f64, [NC][8][64]
-//   b16: three BF16 limbs of the same entries for v_mfma_f32_16x16x32_bf16,
-//        [NC][3][64] x 16 bytes
+//   chunk = (row i, column block q): the pairs (i, j), j in [16q, 16q + 16),
+//   j <= i; NC chunks, listed row by row (crow, FP64 form) and column block by
+//   column block (crow_c, split form).  Every product of row i (coagulation
+//   and remnant targets, and bin i itself, which loses m_i per collision) lies
+//   in the 16-bin window [wb[i], wb[i] + 16).
+//   b64: FP64 B operands of v_mfma_f64_16x16x4f64 in crow order, [NC][8][64]
+//   b16: three BF16 limbs of the same entries for v_mfma_f32_16x16x32_bf16, in
+//        crow_c order, [NC][3][64] x 16 bytes
 struct BatchTables {
     int NC;
     int ok;                      // every row fits its window (else the path is off)
-    const int *crow;             // [NC]  i | q << 16
+    const int *crow;             // [NC]  i | q << 16, row by row
+    const int *crow_c;           // [NC]  i | q << 16, column block by column block
     const int *wb;               // [N]
     const double *b64;
     const uint4 *b16;

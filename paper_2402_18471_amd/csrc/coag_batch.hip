@@ -149,17 +149,22 @@ __global__ void k_batch_rows(Tables T, int *wb, int *bad) {
 }
 
 // one thread per (chunk, lane): the B operands that lane holds for the chunk
-__global__ void k_batch_b(Tables T, int NC, const int *crow, const int *wb, double *b64,
-                          uint4 *b16) {
+__global__ void k_batch_b(Tables T, int NC, const int *crow, const int *crow_c, const int *wb,
+                          double *b64, uint4 *b16) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long)NC * 64) return;
     const int ch = (int)(t >> 6), lane = (int)(t & 63);
-    const int i = crow[ch] & 0xffff, q = crow[ch] >> 16;
-    const int g = lane >> 4, bin = wb[i] + (lane & 15);
+    int i = crow[ch] & 0xffff, q = crow[ch] >> 16;
+    const int g = lane >> 4;
+    int bin = wb[i] + (lane & 15);
     // FP64 operand of MFMA s: K row g <-> pair 16q + 4g + s % 4, kind s / 4
     for (int s = 0; s < 8; ++s)
         b64[((long)ch * 8 + s) * 64 + lane] = d_entry(T, i, 16 * q + 4 * g + (s & 3), s >> 2, bin);
-    // BF16 operand: K rows 8g + e <-> pair 16q + 8 (g % 2) + e, kind g / 2
+    // BF16 operand (chunks in the split form's order): K rows 8g + e <-> pair
+    // 16q + 8 (g % 2) + e, kind g / 2
+    i = crow_c[ch] & 0xffff;
+    q = crow_c[ch] >> 16;
+    bin = wb[i] + (lane & 15);
     union {
         __bf16 h[8];
         uint4 u;
@@ -329,22 +334,22 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         }
     };
 
-    // gain and loss of all 16 cells into net (gain - loss without the
-    // fragment distribution) and phi (fragment mass per top bin).  Each wave
-    // takes a contiguous range of chunks.  The rates, the one stream from HBM,
-    // are loaded kRing chunks ahead into a register ring, the D operands one
-    // chunk ahead.
-    auto contract = [&]() {
+    // ---- FP64 form: gain and loss of all 16 cells into net (gain - loss
+    // without the fragment distribution) and phi (fragment mass per top bin).
+    // Chunks in row-major order, each wave a contiguous range of them: the
+    // gain tile of a row accumulates over the row's chunks and is deposited
+    // when the row changes; the loss of the lighter grain and the fragment mass
+    // are deposited per pair.  The rates, the one stream from HBM, are loaded
+    // kRing chunks ahead into a register ring, the D operands one chunk ahead.
+    auto contract64 = [&]() {
         const int cl = lane & 15, g = lane >> 4;
         const int NC = B.NC;
         const int c0 = (int)((long)wv * NC / kBWaves), c1 = (int)((long)(wv + 1) * NC / kBWaves);
         if (c0 >= c1) return;
         const double *nrow = nv + cl * N;
         double *netc = net + cl * N, *phic = phi + cl * N;
-        const double nmax = PREC == 1 ? ctl[cl].nmax : 0.0;
-        const float *nfr = nf + cl * N;
         const double chi = T.chi;
-        // chunks follow each other row by row: (i, q) -> (i, q + 1) or (i + 1, 0)
+        // (i, q) -> (i, q + 1) or (i + 1, 0)
         auto advance = [](int &i, int &q) {
             if (16 * (q + 1) <= i) ++q;
             else { ++i; q = 0; }
@@ -354,178 +359,246 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         int ri = ci, rq = cq;                       // next chunk to load rates for
         int cur = ci;
         f64x4 acc64 = {0.0, 0.0, 0.0, 0.0};
-        f32x4 acc32 = {0.0f, 0.0f, 0.0f, 0.0f};
-        // accumulator layouts (lane l, register r -> row, column = l % 16):
-        //   v_mfma_f64_16x16x4f64      row l / 16 + 4 r
-        //   v_mfma_f32_16x16x32_bf16   row 4 (l / 16) + r
+        // accumulator layout of v_mfma_f64_16x16x4f64: lane l, register r ->
+        // row (cell) l / 16 + 4 r, column (bin) l % 16
         auto flush = [&](int i) {
             const int bin = B.wb[i] + cl;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int c = PREC == 0 ? g + 4 * r : 4 * g + r;
-                if (PREC == 0) {
-                    atomicAdd(&net[c * N + bin], acc64[r]);
-                } else {
-                    const double f = nv[c * N + i] * ctl[c].nmax;
-                    atomicAdd(&net[c * N + bin], f * (double)acc32[r]);
-                }
-            }
+            for (int r = 0; r < 4; ++r) atomicAdd(&net[(g + 4 * r) * N + bin], acc64[r]);
         };
-        // loss of the lighter grain and fragment deposit of one pair, FP64
-        auto column = [&](int i, int jc, double rsum, double rf, bool frag) {
+        auto column = [&](int i, int jc, double rsum, double rf) {
             atomicAdd(&netc[jc], -mk[jc] * rsum);
-            if (frag) {
-                bool crater;
-                const double fm = frag_mass(mk[i], mk[jc], chi, crater);
-                atomicAdd(&phic[crater ? fcol[jc] : frow[i]], fm * rf);
+            bool crater;
+            const double fm = frag_mass(mk[i], mk[jc], chi, crater);
+            atomicAdd(&phic[crater ? fcol[jc] : frow[i]], fm * rf);
+        };
+        // lane (cell, g): pairs 16q + 4g + s, s = 0..3, both kinds
+        double rkc[kRing][4], rkf[kRing][4], bb[2][8];
+        auto load_k = [&](int i, int q, double (&kc)[4], double (&kf)[4]) {
+            const long prow = (long)i * (i + 1) / 2;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int j = 16 * q + 4 * g + s;
+                const RT *kp = kb + (prow + (j <= i ? j : i)) * 2 * kBC + cl;
+                kc[s] = (double)kp[0];
+                kf[s] = (double)kp[kBC];
             }
         };
-        if (PREC == 0) {
-            // lane (cell, g): pairs 16q + 4g + s, s = 0..3, both kinds
-            double rkc[kRing][4], rkf[kRing][4], bb[2][8];
-            auto load_k = [&](int i, int q, double (&kc)[4], double (&kf)[4]) {
-                const long prow = (long)i * (i + 1) / 2;
+        auto load_b = [&](int ch, double (&b)[8]) {
+            const double *bt = B.b64 + (long)ch * 8 * 64 + lane;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int j = 16 * q + 4 * g + s;
-                    const RT *kp = kb + (prow + (j <= i ? j : i)) * 2 * kBC + cl;
-                    kc[s] = (double)kp[0];
-                    kf[s] = (double)kp[kBC];
-                }
-            };
-            auto load_b = [&](int ch, double (&b)[8]) {
-                const double *bt = B.b64 + (long)ch * 8 * 64 + lane;
+            for (int s = 0; s < 8; ++s) b[s] = bt[s * 64];
+        };
 #pragma unroll
-                for (int s = 0; s < 8; ++s) b[s] = bt[s * 64];
-            };
-#pragma unroll
-            for (int u = 0; u < kRing; ++u)
-                if (c0 + u < c1) {
-                    load_k(ri, rq, rkc[u], rkf[u]);
-                    advance(ri, rq);
-                }
-            load_b(c0, bb[0]);
-            for (int base = c0; base < c1; base += kRing) {
-#pragma unroll
-                for (int u = 0; u < kRing; ++u) {
-                    const int ch = base + u;
-                    if (ch < c1) {
-                        const int i = ci, q = cq;
-                        advance(ci, cq);
-                        if (ch + 1 < c1) load_b(ch + 1, bb[(u + 1) & 1]);
-                        if (i != cur) {
-                            flush(cur);
-                            cur = i;
-                            acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
-                        }
-                        const double ni = nrow[i];
-                        double rc[4], rf[4];
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            const int j = 16 * q + 4 * g + s;
-                            const bool ok = j <= i;
-                            const int jc = ok ? j : i;
-                            const double nn = ok ? ni * nrow[jc] : 0.0;
-                            rc[s] = nn * rkc[u][s];
-                            rf[s] = nn * rkf[u][s];
-                            column(i, jc, rc[s] + rf[s], rf[s], true);
-                        }
-                        const double(&b)[8] = bb[u & 1];
-#pragma unroll
-                        for (int s = 0; s < 4; ++s)
-                            acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rc[s], b[s], acc64, 0, 0, 0);
-#pragma unroll
-                        for (int s = 0; s < 4; ++s)
-                            acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rf[s], b[4 + s], acc64, 0,
-                                                                         0, 0);
-                        if (ch + kRing < c1) {
-                            load_k(ri, rq, rkc[u], rkf[u]);
-                            advance(ri, rq);
-                        }
-                    }
-                }
+        for (int u = 0; u < kRing; ++u)
+            if (c0 + u < c1) {
+                load_k(ri, rq, rkc[u], rkf[u]);
+                advance(ri, rq);
             }
-        } else {
-            // lane (cell, g): pairs 16q + 8 (g % 2) + e, e = 0..7, kind g / 2
-            const int kind = g >> 1;
-            const long cb = cell0 + cl < C ? cell0 + cl : C - 1;
-            const RT *K = (const RT *)(kind ? a.Kf : a.Kc) + cb * P;
-            RT rk[kRing][8];
-            uint4 bb[2][3];
-            auto load_k = [&](int i, int q, RT (&k)[8]) {
-                const long prow = (long)i * (i + 1) / 2;
+        load_b(c0, bb[0]);
+        for (int base = c0; base < c1; base += kRing) {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int j = 16 * q + 8 * (g & 1) + e;
-                    k[e] = K[prow + (j <= i ? j : i)];
-                }
-            };
-            auto load_b = [&](int ch, uint4 (&b)[3]) {
-                const uint4 *bt = B.b16 + (long)ch * 3 * 64 + lane;
-                b[0] = bt[0];
-                b[1] = bt[64];
-                b[2] = bt[128];
-            };
-#pragma unroll
-            for (int u = 0; u < kRing; ++u)
-                if (c0 + u < c1) {
-                    load_k(ri, rq, rk[u]);
-                    advance(ri, rq);
-                }
-            load_b(c0, bb[0]);
-            for (int base = c0; base < c1; base += kRing) {
-#pragma unroll
-                for (int u = 0; u < kRing; ++u) {
-                    const int ch = base + u;
-                    if (ch < c1) {
-                        const int i = ci, q = cq;
-                        advance(ci, cq);
-                        if (ch + 1 < c1) load_b(ch + 1, bb[(u + 1) & 1]);
-                        if (ch > c0) {             // one chunk per FP32 accumulation
-                            flush(cur);
-                            acc32 = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-                        }
+            for (int u = 0; u < kRing; ++u) {
+                const int ch = base + u;
+                if (ch < c1) {
+                    const int i = ci, q = cq;
+                    advance(ci, cq);
+                    if (ch + 1 < c1) load_b(ch + 1, bb[(u + 1) & 1]);
+                    if (i != cur) {
+                        flush(cur);
                         cur = i;
-                        // x = n_j K / max n (FP32, the MFMA operand); the FP64
-                        // rate of the pair for the column terms is (n_i max n) x
-                        const double c64 = nrow[i] * nmax;
-                        float x[8];
-                        auto pairs = [&](bool full) {
+                        acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
+                    }
+                    const double ni = nrow[i];
+                    double rc[4], rf[4];
 #pragma unroll
-                            for (int e = 0; e < 8; ++e) {
-                                const int j = 16 * q + 8 * (g & 1) + e;
-                                const int jc = full ? j : (j <= i ? j : i);
-                                const float xe = nfr[jc] * (float)rk[u][e];
-                                x[e] = full || j <= i ? xe : 0.0f;
-                                const double r = c64 * (double)x[e];
-                                column(i, jc, r, r, kind != 0);
-                            }
-                        };
-                        if (16 * q + 15 <= i) pairs(true);
-                        else pairs(false);
-                        const Limbs8 L = split3x8(x);
-                        union {
-                            uint4 u;
-                            bf16x8 v;
-                        } B0, B1, B2;
-                        B0.u = bb[u & 1][0];
-                        B1.u = bb[u & 1][1];
-                        B2.u = bb[u & 1][2];
-                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B0.v, acc32, 0, 0, 0);
-                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B1.v, acc32, 0, 0, 0);
-                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B0.v, acc32, 0, 0, 0);
-                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B2.v, acc32, 0, 0, 0);
-                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B1.v, acc32, 0, 0, 0);
-                        acc32 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a2, B0.v, acc32, 0, 0, 0);
-                        if (ch + kRing < c1) {
-                            load_k(ri, rq, rk[u]);
-                            advance(ri, rq);
-                        }
+                    for (int s = 0; s < 4; ++s) {
+                        const int j = 16 * q + 4 * g + s;
+                        const bool ok = j <= i;
+                        const int jc = ok ? j : i;
+                        const double nn = ok ? ni * nrow[jc] : 0.0;
+                        rc[s] = nn * rkc[u][s];
+                        rf[s] = nn * rkf[u][s];
+                        column(i, jc, rc[s] + rf[s], rf[s]);
+                    }
+                    const double(&b)[8] = bb[u & 1];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rc[s], b[s], acc64, 0, 0, 0);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rf[s], b[4 + s], acc64, 0, 0, 0);
+                    if (ch + kRing < c1) {
+                        load_k(ri, rq, rkc[u], rkf[u]);
+                        advance(ri, rq);
                     }
                 }
             }
         }
         flush(cur);
+    };
+
+    // ---- split form: the same terms, chunks taken column block by column
+    // block (q outer, row i inner), each wave a contiguous range of them, so a
+    // lane keeps the same lighter grains j over many chunks: the loss of grain
+    // j (m_j times the sum of its rates) and the crater fragments (all at the
+    // top bin of j) are summed in registers and deposited when the column
+    // block changes.  The FP32 gain tile of a chunk (row i's window) is scaled
+    // back and deposited while the next chunk's products run.  Rates are
+    // loaded kRing chunks ahead into a register ring, D operands one ahead.
+    auto contract16 = [&]() {
+        const int cl = lane & 15, g = lane >> 4;
+        const int NC = B.NC;
+        const int c0 = (int)((long)wv * NC / kBWaves), c1 = (int)((long)(wv + 1) * NC / kBWaves);
+        if (c0 >= c1) return;
+        const double *nrow = nv + cl * N;
+        double *netc = net + cl * N, *phic = phi + cl * N;
+        const double nmax = ctl[cl].nmax;
+        const float *nfr = nf + cl * N;
+        const double chi = T.chi;
+        // (i, q) -> (i + 1, q), or the top of the next column block
+        auto advance = [N](int &i, int &q) {
+            if (i + 1 < N) ++i;
+            else { ++q; i = 16 * q; }
+        };
+        const int cr0 = __builtin_amdgcn_readfirstlane(B.crow_c[c0]);
+        int ci = cr0 & 0xffff, cq = cr0 >> 16;     // chunk being processed
+        int ri = ci, rq = cq;                       // next chunk to load rates for
+        // two tiles, used by alternate chunks: a chunk's tile is deposited
+        // after the next chunk's products have been issued into the other one
+        f32x4 acc32[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+        // accumulator layout of v_mfma_f32_16x16x32_bf16: lane l, register r ->
+        // row (cell) 4 (l / 16) + r, column (bin) l % 16
+        auto flush_tile = [&](int i, int t) {
+            const int bin = B.wb[i] + cl;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = 4 * g + r;
+                const double f = nv[c * N + i] * ctl[c].nmax;
+                atomicAdd(&net[c * N + bin], f * (double)acc32[t][r]);
+            }
+            acc32[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        };
+        // this lane's lighter grains in column block q, and their running sums
+        // (fragments only on the lanes that hold fragmenting rates)
+        constexpr int NJ = 8;
+        const bool fraglane = (g >> 1) != 0;
+        auto jof = [&](int q, int u) { return 16 * q + 8 * (g & 1) + u; };
+        double colsum[NJ], fragsum[NJ];
+#pragma unroll
+        for (int u = 0; u < NJ; ++u) colsum[u] = fragsum[u] = 0.0;
+        auto flush_cols = [&](int q) {
+#pragma unroll
+            for (int u = 0; u < NJ; ++u) {
+                const int j = jof(q, u);
+                if (j < N) {
+                    atomicAdd(&netc[j], -mk[j] * colsum[u]);
+                    if (fraglane) atomicAdd(&phic[fcol[j]], fragsum[u]);
+                }
+                colsum[u] = 0.0;
+                fragsum[u] = 0.0;
+            }
+        };
+        // one pair's column terms: rate sum, and fragments (crater: summed for
+        // the block; destroyed target: straight to the top bin of m_i)
+        auto pair_terms = [&](int u, int i, int jc, bool ok, double rsum, double rf) {
+            colsum[u] += rsum;
+            if (fraglane) {
+                bool crater;
+                const double fr = frag_mass(mk[i], mk[jc], chi, crater) * rf;
+                fragsum[u] += crater ? fr : 0.0;
+                if (ok && !crater) atomicAdd(&phic[frow[i]], fr);
+            }
+        };
+        int colq = cq, prev = -1;
+        // lane (cell, g): pairs 16q + 8 (g % 2) + e, e = 0..7, kind g / 2
+        const int kind = g >> 1;
+        const long cb = cell0 + cl < C ? cell0 + cl : C - 1;
+        const RT *K = (const RT *)(kind ? a.Kf : a.Kc) + cb * P;
+        RT rk[kRing][8];
+        uint4 bb[2][3];
+        auto load_k = [&](int i, int q, RT (&k)[8]) {
+            const long prow = (long)i * (i + 1) / 2;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int j = 16 * q + 8 * (g & 1) + e;
+                k[e] = K[prow + (j <= i ? j : i)];
+            }
+        };
+        auto load_b = [&](int ch, uint4 (&b)[3]) {
+            const uint4 *bt = B.b16 + (long)ch * 3 * 64 + lane;
+            b[0] = bt[0];
+            b[1] = bt[64];
+            b[2] = bt[128];
+        };
+#pragma unroll
+        for (int u = 0; u < kRing; ++u)
+            if (c0 + u < c1) {
+                load_k(ri, rq, rk[u]);
+                advance(ri, rq);
+            }
+        load_b(c0, bb[0]);
+        for (int base = c0; base < c1; base += kRing) {
+#pragma unroll
+            for (int u = 0; u < kRing; ++u) {
+                const int ch = base + u;
+                if (ch < c1) {
+                    const int i = ci, q = cq;
+                    advance(ci, cq);
+                    if (ch + 1 < c1) load_b(ch + 1, bb[(u + 1) & 1]);
+                    if (q != colq) {
+                        flush_cols(colq);
+                        colq = q;
+                    }
+                    // x = n_j K / max n (FP32, the MFMA operand); the FP64
+                    // rate of the pair for the column terms is (n_i max n) x
+                    const double c64 = nrow[i] * nmax;
+                    float x[8];
+                    auto pairs = [&](bool full) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const int j = 16 * q + 8 * (g & 1) + e;
+                            const bool ok = full || j <= i;
+                            const int jc = ok ? j : i;
+                            const float xe = nfr[jc] * (float)rk[u][e];
+                            x[e] = ok ? xe : 0.0f;
+                            const double r = c64 * (double)x[e];
+                            pair_terms(e, i, jc, ok, r, r);
+                        }
+                    };
+                    if (16 * q + 15 <= i) pairs(true);
+                    else pairs(false);
+                    const Limbs8 L = split3x8(x);
+                    union {
+                        uint4 u;
+                        bf16x8 v;
+                    } B0, B1, B2;
+                    B0.u = bb[u & 1][0];
+                    B1.u = bb[u & 1][1];
+                    B2.u = bb[u & 1][2];
+                    f32x4 &acc = acc32[u & 1];         // one chunk per FP32 accumulation
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B0.v, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B1.v, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B0.v, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B2.v, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B1.v, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a2, B0.v, acc, 0, 0, 0);
+                    if (prev >= 0) flush_tile(prev, (u + 1) & 1);
+                    prev = i;
+                    if (ch + kRing < c1) {
+                        load_k(ri, rq, rk[u]);
+                        advance(ri, rq);
+                    }
+                }
+            }
+        }
+        flush_tile(prev, (c1 - 1 - c0) & 1);        // the last chunk's tile
+        flush_cols(colq);
+    };
+
+    auto contract = [&]() {
+        if (PREC == 0) contract64();
+        else contract16();
     };
 
     // slope of cell c: net + dE_k sum_{l >= k} phi_l invE_l, into ws slot v
@@ -703,7 +776,7 @@ hipError_t allow_lds_b(K kernel, size_t bytes) {
 size_t batch_tables_bytes(int N) {
     const size_t NC = (size_t)n_chunks(N);
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return al(4 * NC) + al(4 * (size_t)N) + al(8 * NC * 8 * 64) + al(16 * NC * 3 * 64) + 256;
+    return 2 * al(4 * NC) + al(4 * (size_t)N) + al(8 * NC * 8 * 64) + al(16 * NC * 3 * 64) + 256;
 }
 
 hipError_t build_batch_tables(const Tables &T, void *mem, BatchTables *B) {
@@ -712,6 +785,8 @@ hipError_t build_batch_tables(const Tables &T, void *mem, BatchTables *B) {
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     char *p = (char *)mem;
     int *crow = (int *)p;
+    p += al(4 * (size_t)NC);
+    int *crow_c = (int *)p;
     p += al(4 * (size_t)NC);
     int *wb = (int *)p;
     p += al(4 * (size_t)N);
@@ -723,22 +798,27 @@ hipError_t build_batch_tables(const Tables &T, void *mem, BatchTables *B) {
     B->NC = NC;
     B->ok = 0;
     B->crow = crow;
+    B->crow_c = crow_c;
     B->wb = wb;
     B->b64 = b64;
     B->b16 = b16;
     if (N < kWin) return hipSuccess;                 // window wider than the grid: path off
     int *h = (int *)malloc(sizeof(int) * NC);
     if (!h) return hipErrorOutOfMemory;
-    int c = 0;
+    int c = 0;                                       // row by row (FP64 form)
     for (int i = 0; i < N; ++i)
         for (int q = 0; q * 16 <= i; ++q) h[c++] = i | (q << 16);
     hipError_t e = hipMemcpy(crow, h, sizeof(int) * NC, hipMemcpyHostToDevice);
+    c = 0;                                           // column block by column block (split)
+    for (int q = 0; 16 * q < N; ++q)
+        for (int i = 16 * q; i < N; ++i) h[c++] = i | (q << 16);
+    if (e == hipSuccess) e = hipMemcpy(crow_c, h, sizeof(int) * NC, hipMemcpyHostToDevice);
     free(h);
     if (e == hipSuccess) e = hipMemset(bad, 0, sizeof(int));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_rows, dim3((N + 63) / 64), dim3(64), 0, 0, T, wb, bad);
     hipLaunchKernelGGL(k_batch_b, dim3((unsigned)((NC * 64L + 255) / 256)), dim3(256), 0, 0, T, NC,
-                       crow, wb, b64, b16);
+                       crow, crow_c, wb, b64, b16);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int hb = 1;
     if ((e = hipMemcpy(&hb, bad, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) return e;
