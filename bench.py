@@ -214,33 +214,36 @@ def split_error(D, rho_start, sample):
             "status_ok": bool(np.all(b["status"].cpu().numpy() == 0))}
 
 
-def adjoint_ratio(torch, calls=3):
-    """coag_step_backward time / forward (rates + step) time, per call, on the
-    64x32 x 100 adjoint disc (HIP events on the stream)."""
+def adjoint_ratio(torch, reps=3):
+    """Backward / forward time of the same coagulation call on the 64x32 x 100
+    adjoint disc: the first call from the initial state (rates + ADAPTIVE
+    step, steps recorded), then coag_step_backward of that call (which
+    recomputes the rates and the stage states); HIP events on the stream,
+    mean over reps after one warm-up."""
     D = Disc("disc64x32_n100_adj", torch)
-    f = D.forward(calls, 1, False)
-    # the first call from the initial state, its steps recorded, is the one differentiated
     rho_in = D.t(D.d["rho"])
-    Kc, Kf = D.ctx.coag_rates(D.cells, D.v_dust, D.v_frag)
-    a = D.ctx.coag_step(rho_in.clone(), Kc, Kf, float(D.d["dt"]), max_sub=64)
-    nsub, hlog = a["nsub"], a["h_log"]
+    dt = float(D.d["dt"])
     g_out = torch.ones((D.C, D.N), dtype=torch.float64, device=D.dev) / rho_in.sum(1, keepdim=True)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    D.ctx.coag_step_backward(rho_in, D.cells, D.v_dust, D.v_frag, hlog, nsub, g_out)
-    torch.cuda.synchronize()
-    ms = []
-    for _ in range(calls):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    fwd, bwd = [], []
+    for r in range(reps + 1):
+        rho = rho_in.clone()
         ev[0].record(D.stream)
-        D.ctx.coag_step_backward(rho_in, D.cells, D.v_dust, D.v_frag, hlog, nsub, g_out)
+        Kc, Kf = D.ctx.coag_rates(D.cells, D.v_dust, D.v_frag)
+        a = D.ctx.coag_step(rho, Kc, Kf, dt, max_sub=64)
         ev[1].record(D.stream)
+        ev[2].record(D.stream)
+        D.ctx.coag_step_backward(rho_in, D.cells, D.v_dust, D.v_frag, a["h_log"], a["nsub"], g_out)
+        ev[3].record(D.stream)
         torch.cuda.synchronize()
-        ms.append(ev[0].elapsed_time(ev[1]))
-    fwd = float(np.mean(f["rates_ms"] + f["step_ms"]))
-    return {"workload": D.cfg.name, "backward_ms": float(np.mean(ms)), "forward_ms": fwd,
-            "adjoint_over_forward": float(np.mean(ms)) / fwd,
-            "note": "backward of the first call from the initial state (recomputes rates and "
-                    "stage states); forward = rates + ADAPTIVE step per call; accepted sub-steps "
-                    f"per cell in the differentiated call {float(nsub.float().mean()):.2f}"}
+        if r:
+            fwd.append(ev[0].elapsed_time(ev[1]))
+            bwd.append(ev[2].elapsed_time(ev[3]))
+    f, b = float(np.mean(fwd)), float(np.mean(bwd))
+    return {"workload": D.cfg.name, "backward_ms": b, "forward_ms": f, "adjoint_over_forward": b / f,
+            "note": "same call both ways: the first call from the initial state, "
+                    f"{float(a['nsub'].float().mean()):.2f} accepted sub-steps per cell; forward = "
+                    "rates + ADAPTIVE step; backward recomputes rates and stage states"}
 
 
 def main():

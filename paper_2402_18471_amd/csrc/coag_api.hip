@@ -345,7 +345,8 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
     const size_t P = ctx->P, N = ctx->N;
     const size_t bK = align256(8 * P * (size_t)C);
     const size_t bY = align256(8 * N * (size_t)(log_stride + 1) * (size_t)C);
-    if (int r = ensure_ws(ctx, 4 * bK + bY)) return r;
+    const size_t bZ = align256(8 * N * 2 * (size_t)log_stride * (size_t)C);
+    if (int r = ensure_ws(ctx, 4 * bK + bY + bZ)) return r;
     char *w = (char *)ctx->ws;
     double *Kc = (double *)w, *Kf = (double *)(w + bK), *gKc = (double *)(w + 2 * bK),
            *gKf = (double *)(w + 3 * bK), *Ys = (double *)(w + 4 * bK);
@@ -359,6 +360,7 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
     a.gKc = gKc;
     a.gKf = gKf;
     a.Ys = Ys;
+    a.Zs = (double *)(w + 4 * bK + bY);
     a.h_log = h_log;
     a.log_stride = log_stride;
     a.nsub = nsub;

@@ -363,17 +363,23 @@ __global__ __launch_bounds__(BLOCK) void k_step(Tables T, StepArgs a) {
 //     mu1 = h 2/9 lam + h/2 v2,   v1 = J(y)^T mu1,   lam += v1 + v2 + v3.
 //   gKc, gKf collect dJ/dKc, dJ/dKf per pair for the rate chain rule.
 // ---------------------------------------------------------------------------
+// Reverse sweep over the frozen steps of one cell.  The forward replay keeps
+// every step's state and its two inner stage states (y2, y3) in the workspace,
+// so the sweep evaluates only the three vector-Jacobian products per step.
+// dJ/dKc, dJ/dKf are summed in LDS over the whole sweep when they fit
+// (gk_lds), else in the global workspace.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_adjoint(Tables T, AdjArgs a) {
+__global__ __launch_bounds__(BLOCK) void k_adjoint(Tables T, AdjArgs a, int gk_lds) {
     extern __shared__ double lds[];
     const long c = blockIdx.x;
     const int N = T.N, P = T.P;
-    double *lam = lds, *mu = lds + N, *k1 = lds + 2 * N, *k2 = lds + 3 * N, *y2 = lds + 4 * N,
-           *y3 = lds + 5 * N, *v3 = lds + 6 * N, *v2 = lds + 7 * N, *v1 = lds + 8 * N,
-           *scratch = lds + 9 * N;
+    double *lam = lds, *mu = lds + N, *k1 = lds + 2 * N, *k2 = lds + 3 * N, *k3 = lds + 4 * N,
+           *v3 = lds + 6 * N, *v2 = lds + 7 * N, *v1 = lds + 8 * N, *scratch = lds + 9 * N;
     const double *Kc = a.Kc + c * P, *Kf = a.Kf + c * P;
-    double *gKc = a.gKc + c * P, *gKf = a.gKf + c * P;
+    double *gKc = gk_lds ? lds + 14 * N : a.gKc + c * P;
+    double *gKf = gk_lds ? lds + 14 * N + P : a.gKf + c * P;
     double *Ys = a.Ys + c * (long)(a.log_stride + 1) * N;
+    double *Zs = a.Zs + c * (long)a.log_stride * 2 * N;      // y2, y3 of every step
     const double *hl = a.h_log + c * (long)a.log_stride;
     int n = a.nsub[c];
     const bool ok = n >= 0 && n <= a.log_stride;
@@ -387,6 +393,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Tables T, AdjArgs a) {
     for (int s = 0; s < n; ++s) {                     // forward replay
         const double *y = Ys + (long)s * N;
         double *yn = Ys + (long)(s + 1) * N;
+        double *y2 = Zs + (long)s * 2 * N, *y3 = y2 + N;
         const double h = hl[s];
         rhs_cell<BLOCK>(T, Kc, Kf, y, k1, scratch);
         for (int k = threadIdx.x; k < N; k += BLOCK) y2[k] = y[k] + 0.5 * h * k1[k];
@@ -394,22 +401,18 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Tables T, AdjArgs a) {
         rhs_cell<BLOCK>(T, Kc, Kf, y2, k2, scratch);
         for (int k = threadIdx.x; k < N; k += BLOCK) y3[k] = y[k] + 0.75 * h * k2[k];
         __syncthreads();
-        rhs_cell<BLOCK>(T, Kc, Kf, y3, v3, scratch);   // k3 (v3 as storage)
+        rhs_cell<BLOCK>(T, Kc, Kf, y3, k3, scratch);
         for (int k = threadIdx.x; k < N; k += BLOCK)
-            yn[k] = y[k] + h * (2.0 / 9.0 * k1[k] + 1.0 / 3.0 * k2[k] + 4.0 / 9.0 * v3[k]);
+            yn[k] = y[k] + h * (2.0 / 9.0 * k1[k] + 1.0 / 3.0 * k2[k] + 4.0 / 9.0 * k3[k]);
         __syncthreads();
     }
     for (int k = threadIdx.x; k < N; k += BLOCK) lam[k] = a.g_out[c * N + k];
     __syncthreads();
     for (int s = n - 1; s >= 0; --s) {
         const double *y = Ys + (long)s * N;
+        const double *y2 = Zs + (long)s * 2 * N, *y3 = y2 + N;
         const double h = hl[s];
-        rhs_cell<BLOCK>(T, Kc, Kf, y, k1, scratch);
-        for (int k = threadIdx.x; k < N; k += BLOCK) y2[k] = y[k] + 0.5 * h * k1[k];
-        __syncthreads();
-        rhs_cell<BLOCK>(T, Kc, Kf, y2, k2, scratch);
         for (int k = threadIdx.x; k < N; k += BLOCK) {
-            y3[k] = y[k] + 0.75 * h * k2[k];
             mu[k] = h * (4.0 / 9.0) * lam[k];
             v3[k] = 0.0;
             v2[k] = 0.0;
@@ -427,6 +430,12 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Tables T, AdjArgs a) {
         __syncthreads();
     }
     for (int k = threadIdx.x; k < N; k += BLOCK) a.g_in[c * N + k] = ok ? lam[k] : NAN;
+    if (gk_lds) {
+        for (int p = threadIdx.x; p < P; p += BLOCK) {
+            a.gKc[c * P + p] = gKc[p];
+            a.gKf[c * P + p] = gKf[p];
+        }
+    }
 }
 
 // dJ/dalpha and dJ/dv_frag per cell from dJ/dKc, dJ/dKf and the hand-derived
@@ -588,9 +597,12 @@ hipError_t launch_adjoint(const Tables &T, long C, const AdjArgs &a, const CellA
                           const double *v_dust, const double *v_frag, double *g_alpha,
                           double *g_vfrag, hipStream_t st) {
     if (C == 0) return hipSuccess;
-    if (hipError_t e = allow_lds(k_adjoint<kBlock>, lds_bytes(14 * T.N))) return e;
-    hipLaunchKernelGGL(k_adjoint<kBlock>, dim3((unsigned)C), dim3(kBlock), lds_bytes(14 * T.N), st,
-                       T, a);
+    // dJ/dK in LDS when 2P more doubles fit beside the 14N of the sweep
+    const size_t with_gk = lds_bytes(14 * T.N + 2 * T.P);
+    const int gk_lds = with_gk <= 160 * 1024;
+    const size_t bytes = gk_lds ? with_gk : lds_bytes(14 * T.N);
+    if (hipError_t e = allow_lds(k_adjoint<kBlock>, bytes)) return e;
+    hipLaunchKernelGGL(k_adjoint<kBlock>, dim3((unsigned)C), dim3(kBlock), bytes, st, T, a, gk_lds);
     hipLaunchKernelGGL(k_rate_grad<kBlock>, dim3((unsigned)C), dim3(kBlock),
                        lds_bytes(4 * T.N + 64), st, T, cells, v_dust, v_frag, a.gKc, a.gKf,
                        g_alpha, g_vfrag);

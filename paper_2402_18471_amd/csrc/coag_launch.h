@@ -29,6 +29,7 @@ struct AdjArgs {
     const double *Kc, *Kf;       // rates of the cells (workspace)
     double *gKc, *gKf;           // dJ/dKc, dJ/dKf (workspace)
     double *Ys;                  // step-start states (workspace) [C][log_stride+1][N]
+    double *Zs;                  // inner stage states y2, y3 (workspace) [C][log_stride][2][N]
     const double *h_log;
     int log_stride;
     const int32_t *nsub;
