@@ -312,6 +312,8 @@ def main():
             "speedup_vs_fp64": (s["acc"] / s["wall"]) / (f["acc"] / f["wall"]),
             "error_vs_fp64": split_error(D, f["rho"], np.arange(0, C, max(1, C // 512))),
         }
+    free, total = torch.cuda.mem_get_info()
+    out["device_memory_used_gb"] = (total - free) / 1e9    # rates, workspaces, torch cache
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(torch)
     if not args.no_cpu_baseline:
