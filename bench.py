@@ -73,7 +73,54 @@ def parse():
                     help="FP64 step kernel (cell: one workgroup per cell)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_LOG"),
+                    help="no GPU work: write the counter summary the roofline's traffic is read "
+                         "from, from the counter_collection.csv files of a FETCH_SIZE and a "
+                         "WRITE_SIZE rocprofv3 pass over 'bench.py --steps 1 --warmup 1 "
+                         "--no-cpu-baseline --no-adjoint --calibrate-copy', and that run's output")
     return ap.parse_args()
+
+
+def summarize_counters(fetch_csv, write_csv, bench_log):
+    """Per-cell-RHS HBM bytes of the two step forms from rocprofv3 counter
+    passes over one 'bench.py --steps 1 --warmup 1 --calibrate-copy' run.
+    Each form launches the step kernel three times there (warm-up call, timed
+    call, error sample); the timed call is the second.  FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) are scaled by what they read for the final
+    1 GiB device copy."""
+    import csv
+    import hashlib
+
+    def per_dispatch(path):
+        rows = {}
+        for r in csv.DictReader(open(path)):
+            rows.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        return [rows[k] for k in sorted(rows)]
+
+    line = [ln for ln in open(bench_log) if ln.startswith("{")][-1]
+    b = json.loads(line)
+    rhs = {"fp64": b["rhs_per_call"], "split": b["split_bf16"]["rhs_per_call"]}
+    out = {"kernel_source": os.path.relpath(KERNEL_SRC, ROOT),
+           "kernel_source_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest(),
+           "workload": f"{b['config']['workload']}, second coagulation call from the MRN start "
+                       "(bench.py --steps 1 --warmup 1)",
+           "cell_rhs_in_profiled_launch": rhs, "calibration": {"copy_bytes": 1 << 30}}
+    cal = out["calibration"]
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        d = per_dispatch(path)
+        copy = [v for k, v in d if "copyBuffer" in k][-1]
+        cal[name + "_KiB"] = copy
+        factor = cal["copy_bytes"] / (copy * 1024.0)
+        cal[("fetch" if name == "FETCH_SIZE" else "write") + "_factor"] = factor
+        for kind, tag in (("fp64", "k_step_batch<0"), ("split", "k_step_batch<1")):
+            launches = [v for k, v in d if tag in k]
+            if len(launches) != 3:
+                raise SystemExit(f"{path}: expected 3 {tag} launches, found {len(launches)}")
+            key = ("fetch" if name == "FETCH_SIZE" else "write") + "_bytes_per_cell_rhs"
+            out.setdefault(kind, {})[key] = launches[1] * 1024.0 * factor / rhs[kind]
+    with open(COUNTERS, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def cpu_baseline(cfg, disc_mod, n_cells, target_s=10.0, max_calls=2000):
@@ -146,7 +193,8 @@ class Disc:
         nrej = torch.zeros((n, C), dtype=torch.int32, device=self.dev)
         status = torch.zeros(C, dtype=torch.int32, device=self.dev)
         max_sub = 4096
-        Kc = torch.empty((C, self.P), dtype=torch.float32 if f32 else torch.float64, device=self.dev)
+        Kc = (torch.empty(self.ctx.blocked_shape(C), dtype=torch.float32, device=self.dev) if f32
+              else torch.empty((C, self.P), dtype=torch.float64, device=self.dev))
         Kf = torch.empty_like(Kc)
         tol = L.Tol(1e-2, 1e-10, 1e-12, max_sub, L.ADAPTIVE,
                     L.PREC_SPLIT_BF16 if split else L.PREC_FP64, 0, 1 if f32 else 0)
@@ -248,6 +296,9 @@ def adjoint_ratio(torch, reps=3):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(the cell-parallel path would shard by radial rings, see DESIGN.md)"}))

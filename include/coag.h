@@ -101,7 +101,8 @@ typedef struct {
    prec: COAG_PREC_*.  renorm: non-zero rescales each cell's state after the
    call so that its total mass equals the total at entry (COAG_PREC_SPLIT_BF16
    always does).  rates_f32: 1 if the Kc, Kf handed to coag_step are float
-   arrays from coag_rates_f32 (COAG_PREC_SPLIT_BF16 only), 0 for double. */
+   arrays in the 16-cell-blocked layout of coag_rates_f32
+   (COAG_PREC_SPLIT_BF16 only), 0 for double [C][P]. */
 typedef struct {
     double rtol, atol_rel, h_min_rel;
     int32_t max_sub, mode, prec, renorm, rates_f32;
@@ -147,9 +148,12 @@ const char *coag_last_error(const coag_ctx *ctx);
 int coag_rates(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
                const double *v_frag, double *Kc, double *Kf, void *stream);
 
-/* The same rates rounded to FP32 (Kc, Kf float [C][P] DEVICE out), for the
-   split-BF16 step (coag_tol.rates_f32 = 1), which then streams half the bytes
-   per right-hand side.  Errors as coag_rates. */
+/* The same rates rounded to FP32, for the split-BF16 step (coag_tol.rates_f32
+   = 1), which then streams half the bytes per right-hand side, in whole
+   64-byte runs.  Layout: 16-cell blocks, [ceil(C/16)][P][16] floats, the rate
+   of cell c and pair p at ((c / 16) * P + p) * 16 + c % 16; Kc, Kf DEVICE out,
+   each ceil(C/16) * 16 * P floats, caller-owned; the padding cells of the last
+   block are written as zeros.  Errors as coag_rates. */
 int coag_rates_f32(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
                    const double *v_frag, float *Kc, float *Kf, void *stream);
 
@@ -174,8 +178,9 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
    a clipped accepted step leaves h unchanged.  FIXED: nsub[c] equal steps of
    dt/nsub[c].  REPLAY: nsub[c] steps of the sizes h_log[c][0..nsub[c]).
      rho     [C][N]        DEVICE in/out
-     Kc, Kf  [C][P]        DEVICE in (from coag_rates, or any kernel): double, or
-                           float when tol->rates_f32 = 1
+     Kc, Kf  [C][P]        DEVICE in (from coag_rates, or any kernel): double; or,
+                           when tol->rates_f32 = 1, float in the 16-cell-blocked
+                           layout of coag_rates_f32
      h       [C]           DEVICE in/out (ADAPTIVE): h <= 0 on entry starts with dt;
                            on exit the controller's next (unclipped) step size
      nsub    [C] int32     DEVICE out (ADAPTIVE: accepted steps) or in (FIXED, REPLAY)

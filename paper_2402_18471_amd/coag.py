@@ -95,16 +95,22 @@ class CoagContext:
                                          _ptr(Kc), _ptr(Kf), _stream()))
         return Kc, Kf
 
+    def blocked_shape(self, C):
+        """Shape of the 16-cell-blocked FP32 rates of C cells: the rate of
+        cell c, pair p at [c // 16, p, c % 16]."""
+        return ((C + 15) // 16, self.P, 16)
+
     def coag_rates_f32(self, cells, v_dust, v_frag, Kc=None, Kf=None):
-        """The rates rounded to float32, for split-precision steps."""
+        """The rates rounded to float32, for split-precision steps, in the
+        16-cell-blocked layout (blocked_shape(C))."""
         C = int(v_frag.shape[0])
         cs, keep = self._cells(cells, C)
         _dev(v_dust, shape=(C, self.N, 3), name="v_dust")
         _dev(v_frag, shape=(C,), name="v_frag")
         dev = v_frag.device
-        f32 = torch.float32
-        Kc = torch.empty((C, self.P), dtype=f32, device=dev) if Kc is None else _dev(Kc, f32, (C, self.P), "Kc")
-        Kf = torch.empty((C, self.P), dtype=f32, device=dev) if Kf is None else _dev(Kf, f32, (C, self.P), "Kf")
+        f32, shp = torch.float32, self.blocked_shape(C)
+        Kc = torch.empty(shp, dtype=f32, device=dev) if Kc is None else _dev(Kc, f32, shp, "Kc")
+        Kf = torch.empty(shp, dtype=f32, device=dev) if Kf is None else _dev(Kf, f32, shp, "Kf")
         self._check(self._lib.coag_rates_f32(self._h, C, ct.byref(cs), _ptr(v_dust), _ptr(v_frag),
                                              _ptr(Kc), _ptr(Kf), _stream()))
         return Kc, Kf
@@ -122,15 +128,16 @@ class CoagContext:
                   atol_rel=1e-10, h_min_rel=1e-12, max_sub=10000, renorm=False, nsub=None,
                   h_log=None, log=True):
         """Advances rho (in place) by dt; returns dict(rho, h, nsub, nrej, h_log, status).
-        Kc, Kf: float64 from coag_rates, or float32 from coag_rates_f32 (split
-        precision only)."""
+        Kc, Kf: float64 [C][P] from coag_rates, or float32 in the blocked
+        layout of coag_rates_f32 (split precision only)."""
         C = int(rho.shape[0])
         dev = rho.device
         _dev(rho, shape=(C, self.N), name="rho")
         rates_f32 = Kc.dtype == torch.float32
         rdt = torch.float32 if rates_f32 else torch.float64
-        _dev(Kc, dtype=rdt, shape=(C, self.P), name="Kc")
-        _dev(Kf, dtype=rdt, shape=(C, self.P), name="Kf")
+        shp = self.blocked_shape(C) if rates_f32 else (C, self.P)
+        _dev(Kc, dtype=rdt, shape=shp, name="Kc")
+        _dev(Kf, dtype=rdt, shape=shp, name="Kf")
         if h is None:
             h = torch.zeros(C, dtype=torch.float64, device=dev)
         _dev(h, shape=(C,), name="h")

@@ -229,8 +229,9 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
     // then kind (Kc, Kf), then the 16 cells, so that every right-hand side
     // streams whole cache lines (rows of [C][P] are P elements apart).  Staged
     // through LDS tiles of TP pairs (rows padded by one element against bank
-    // conflicts).  The split form, bound by its vector work rather than by the
-    // rate stream, reads [C][P] directly.
+    // conflicts).  The split form reads FP32 rates in the 16-cell-blocked
+    // layout that coag_rates_f32 writes (whole 64-byte runs per pair), and FP64
+    // rates as [C][P].
     RT *const kb = wk + (long)blockIdx.x * P * 2 * kBC;
     if (PREC == 0) {
         RT *tile = (RT *)lds;
@@ -513,8 +514,12 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         int colq = cq, prev = -1;
         // lane (cell, g): pairs 16q + 8 (g % 2) + e, e = 0..7, kind g / 2
         const int kind = g >> 1;
+        // FP32 rates: pair p of the batch's cell cl at p * 16 + cl (padding
+        // cells hold zeros); FP64 rates: [C][P], cells past C read cell C - 1
+        constexpr bool blk = sizeof(RT) == 4;
+        constexpr long ks = blk ? 16 : 1;
         const long cb = cell0 + cl < C ? cell0 + cl : C - 1;
-        const RT *K = (const RT *)(kind ? a.Kf : a.Kc) + cb * P;
+        const RT *K = (const RT *)(kind ? a.Kf : a.Kc) + (blk ? cell0 * P + cl : cb * P);
         RT rk[kRing][8];
         uint4 bb[2][3];
         auto load_k = [&](int i, int q, RT (&k)[8]) {
@@ -522,7 +527,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int j = 16 * q + 8 * (g & 1) + e;
-                k[e] = K[prow + (j <= i ? j : i)];
+                k[e] = K[(prow + (j <= i ? j : i)) * ks];
             }
         };
         auto load_b = [&](int ch, uint4 (&b)[3]) {

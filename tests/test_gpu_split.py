@@ -60,14 +60,40 @@ CASES = [("disc64x32_n100", 8, 4), ("disc256x128_n150", 8, 4), ("disc512x256_n20
          ("disc256x128_n150", 5, 7)]
 
 
-@pytest.mark.parametrize("case", CASES[:3])
+def _unblock(K, C):
+    """[ceil(C/16)][P][16] -> [C][P]; also returns the padding cells."""
+    x = _np(K).astype(np.float64).transpose(0, 2, 1).reshape(-1, K.shape[1])
+    return x[:C], x[C:]
+
+
+# (13, 3) and (5, 7): a ragged last block of 16 cells.  The writer keeps
+# fewer per-grain values in LDS as the grid grows: all of them at 100 and 150
+# bins, St and the velocity at 200, St alone at 320 bins.
+RATE_CASES = CASES[:3] + [("disc64x32_n100", 13, 3), ("disc64x32_n100", 5, 7)]
+
+
+@pytest.mark.parametrize("case", RATE_CASES + [("disc64x32_n100", 5, 7, 320)])
 def test_rates_f32(O, case):
-    cfg, g, d, ctx, cells = _case(O, *case)
+    if len(case) == 4:
+        from paper_2402_18471_amd import disc
+        from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
+        cfg = disc.scaled(disc.CONFIGS[case[0]], case[1], case[2], case[3])
+        m, me, s = coag_mass_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
+        g = O.make_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
+        d = disc.make_disc(cfg, g.s)
+        ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
+        cells = {k: _t(v) for k, v in d["cells"].items()}
+    else:
+        cfg, g, d, ctx, cells = _case(O, *case)
+    C = cfg.n_cells
     Kc, Kf = ctx.coag_rates_f32(cells, _t(d["v_dust"]), _t(d["v_frag"]))
     torch.cuda.synchronize()
+    assert tuple(Kc.shape) == ((C + 15) // 16, ctx.P, 16)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
-    for a, b in ((_np(Kc).astype(np.float64), oKc), (_np(Kf).astype(np.float64), oKf)):
+    for K, b in ((Kc, oKc), (Kf, oKf)):
+        a, pad = _unblock(K, C)
         assert np.all(np.abs(a - b) <= 2.0 ** -24 * np.abs(b) + 1e-12 * (oKc + oKf))
+        assert pad.shape[0] == (-C) % 16 and np.all(pad == 0.0)
 
 
 @pytest.mark.parametrize("rates", ["f64", "f32"])
