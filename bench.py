@@ -1,14 +1,15 @@
 """Throughput of the coagulation-fragmentation hot path on one MI355X.
 
 One bench step = one coagulation call on every cell of the synthetic disc:
-coag_rates (pair rates from the gas state and dust velocities) followed by
-coag_step (adaptive BS3(2) sub-cycling over dt = 10 yr), the state carried
-from step to step.  The metric is accepted cell-steps per second, a
+coag_rates_blocked (pair rates from the gas state and dust velocities, in the
+16-cell-blocked layout the batched step reads) followed by coag_step
+(adaptive BS3(2) sub-cycling over dt = 10 yr), the state carried from step to
+step.  The metric is accepted cell-steps per second, a
 cell-step being one accepted BS3 sub-step of one cell (three right-hand-side
 evaluations, error estimate and FP64 update).
 
 Measured on the 256x128-cell, 150-bin disc:
-  value          FP64 path (batched FP64 matrix-core step)
+  value          FP64 path (FP64 rates, batched FP64 matrix-core step)
   split_bf16     split-BF16 step with FP32 rates: throughput, speedup over the
                  FP64 path, and its per-bin error against the FP64 GPU path
                  (replaying the same steps) on a stratified sample of cells
@@ -57,6 +58,28 @@ def profiled_traffic(rhs_per_launch, kind):
         return None
     per = c[kind]["fetch_bytes_per_cell_rhs"] + c[kind]["write_bytes_per_cell_rhs"]
     return float(np.mean(rhs_per_launch) * per / 1e9)
+
+
+def progress(msg):
+    """A line on stderr per finished phase (stdout carries only the JSON)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def lockstep_efficiency(attempts, prev):
+    """Share of the batched step's cell-slots that do useful work: 16 cells
+    advance in lockstep, so a batch costs 16 (1 + 3 max attempts) cell
+    right-hand sides.  Also what grouping the cells by the previous call's
+    attempts (a stable sort) would give."""
+    def eff(a):
+        C = a.shape[1]
+        pad = (-C) % 16
+        b = np.pad(a, ((0, 0), (0, pad)))
+        used = (3 * a + 1).sum()
+        cost = (16 * (3 * b.reshape(a.shape[0], -1, 16).max(axis=2) + 1)).sum()
+        return float(used / cost)
+    order = np.argsort(prev, axis=1, kind="stable")
+    return {"efficiency": eff(attempts),
+            "efficiency_grouped_by_previous_call": eff(np.take_along_axis(attempts, order, axis=1))}
 
 
 def parse():
@@ -164,6 +187,7 @@ class Disc:
         m, me, s = coag_mass_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
         self.d = d = disc.make_disc(cfg, s)
         self.C, self.N = cfg.n_cells, cfg.n_bins
+        self.kernel = kernel
         self.t = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt,
                                                               device=dev)
         self.ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
@@ -186,6 +210,9 @@ class Disc:
         torch, L = self.torch, self.L
         C = self.C
         f32 = split
+        # rates layout: 16-cell-blocked (float for split, double for the
+        # batched FP64 step); [C][P] for the per-cell FP64 kernel
+        blk = split or self.kernel == "batch"
         rho = (self.t(self.d["rho"]) if rho is None else rho.clone())
         h = torch.zeros(C, dtype=torch.float64, device=self.dev)
         n = warmup + steps
@@ -193,12 +220,12 @@ class Disc:
         nrej = torch.zeros((n, C), dtype=torch.int32, device=self.dev)
         status = torch.zeros(C, dtype=torch.int32, device=self.dev)
         max_sub = 4096
-        Kc = (torch.empty(self.ctx.blocked_shape(C), dtype=torch.float32, device=self.dev) if f32
-              else torch.empty((C, self.P), dtype=torch.float64, device=self.dev))
+        Kc = torch.empty(self.ctx.blocked_shape(C) if blk else (C, self.P),
+                         dtype=torch.float32 if f32 else torch.float64, device=self.dev)
         Kf = torch.empty_like(Kc)
         tol = L.Tol(1e-2, 1e-10, 1e-12, max_sub, L.ADAPTIVE,
-                    L.PREC_SPLIT_BF16 if split else L.PREC_FP64, 0, 1 if f32 else 0)
-        rates_fn = self.lib.coag_rates_f32 if f32 else self.lib.coag_rates
+                    L.PREC_SPLIT_BF16 if split else L.PREC_FP64, 0,
+                    L.RATES_BLK32 if f32 else (L.RATES_BLK64 if blk else L.RATES_CP64))
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n)]
         p, sp, h_ = self.p, self.sp, self.ctx._h
         dt = float(self.d["dt"])
@@ -206,8 +233,13 @@ class Disc:
         def one(i):
             e = ev[i]
             e[0].record(self.stream)
-            L.check(rates_fn(h_, C, ct.byref(self.cs), p(self.v_dust), p(self.v_frag), p(Kc), p(Kf),
-                             sp), h_)
+            if blk:
+                L.check(self.lib.coag_rates_blocked(h_, C, ct.byref(self.cs), p(self.v_dust),
+                                                    p(self.v_frag), 1 if f32 else 0, p(Kc), p(Kf),
+                                                    sp), h_)
+            else:
+                L.check(self.lib.coag_rates(h_, C, ct.byref(self.cs), p(self.v_dust),
+                                            p(self.v_frag), p(Kc), p(Kf), sp), h_)
             e[1].record(self.stream)
             L.check(self.lib.coag_step(h_, C, p(rho), p(Kc), p(Kf), dt, p(h), ct.byref(tol),
                                        p(nsub[i]), p(nrej[i]), None, p(status), sp), h_)
@@ -224,7 +256,8 @@ class Disc:
         sl = slice(warmup, n)
         ns = nsub[sl].cpu().numpy().astype(np.int64)
         nr = nrej[sl].cpu().numpy().astype(np.int64)
-        return dict(wall=wall, acc=int(ns.sum()), rej=int(nr.sum()), ns=ns, nr=nr,
+        prev = (nsub + nrej)[warmup - 1:n - 1].cpu().numpy() if warmup > 0 else ns + nr
+        return dict(wall=wall, acc=int(ns.sum()), rej=int(nr.sum()), ns=ns, nr=nr, prev_attempts=prev,
                     rates_ms=np.array([ev[i][0].elapsed_time(ev[i][1]) for i in range(warmup, n)]),
                     step_ms=np.array([ev[i][1].elapsed_time(ev[i][2]) for i in range(warmup, n)]),
                     failed=int((status.cpu().numpy() != 0).sum()), rho=rho)
@@ -244,7 +277,7 @@ def split_error(D, rho_start, sample):
     rho0 = rho_start[D.t(idx, torch.int64)].contiguous()
     dt = 20.0 * float(D.d["dt"])
     K64 = D.ctx.coag_rates(cells, vd, vf)
-    K32 = D.ctx.coag_rates_f32(cells, vd, vf)
+    K32 = D.ctx.coag_rates_blocked(cells, vd, vf)
     a = D.ctx.coag_step(rho0.clone(), *K64, dt, max_sub=512)
     b = D.ctx.coag_step(rho0.clone(), *K32, dt, mode=L.REPLAY, prec=L.PREC_SPLIT_BF16,
                         nsub=a["nsub"].clone(), h_log=a["h_log"])
@@ -307,10 +340,13 @@ def main():
     from paper_2402_18471_amd import disc
 
     D = Disc(args.config, torch, args.kernel)
+    progress(f"disc {args.config} ready")
     C, N, P = D.C, D.N, D.P
     K, W = args.steps, args.warmup
     f = D.forward(K, W, False)
+    progress(f"fp64: {K} calls, {f['wall'] / K * 1e3:.2f} ms per call")
     attempts = f["ns"] + f["nr"]                              # [steps][C]
+    lockstep = lockstep_efficiency(attempts, f["prev_attempts"])
     rhs_per_launch = (3 * attempts + 1).sum(axis=1)            # k1 once per cell per call
     bytes_per_launch = rhs_per_launch * (16.0 * P + 16.0 * N)
     achieved = float(np.mean(bytes_per_launch / (f["step_ms"] * 1e-3)) / 1e9)
@@ -336,6 +372,7 @@ def main():
         "step_ms": float(f["step_ms"].mean()),
         "cells_failed": f["failed"],
         "rhs_per_call": float(np.mean(rhs_per_launch)),
+        "lockstep": lockstep,
         "roofline": {"bound": "hbm", "kernel": "coag_step FP64 (k_step_batch)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -346,6 +383,7 @@ def main():
     }
     if not args.no_split:
         s = D.forward(K, W, True)
+        progress(f"split: {K} calls, {s['wall'] / K * 1e3:.2f} ms per call")
         s_rhs = (3 * (s["ns"] + s["nr"]) + 1).sum(axis=1)
         s_alg = s_rhs * (8.0 * P + 16.0 * N)          # FP32 rates
         s_ach = float(np.mean(s_alg / (s["step_ms"] * 1e-3)) / 1e9)
@@ -367,7 +405,9 @@ def main():
     out["device_memory_used_gb"] = (total - free) / 1e9    # rates, workspaces, torch cache
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(torch)
+        progress("adjoint timed")
     if not args.no_cpu_baseline:
+        progress("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(D.cfg, disc, args.cpu_sample_cells)
     if args.calibrate_copy:
         x = torch.ones(1 << 27, dtype=torch.float64, device=D.dev)

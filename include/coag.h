@@ -72,6 +72,15 @@ enum { COAG_PREC_FP64 = 0, COAG_PREC_SPLIT_BF16 = 1 };
 /* step-size modes of coag_step */
 enum { COAG_ADAPTIVE = 0, COAG_FIXED = 1, COAG_REPLAY = 2 };
 
+/* layouts of the rates handed to coag_step (coag_tol.rates_layout):
+   CP64  : double [C][P], pair p of cell c at c * P + p (coag_rates);
+   BLK32 : float, 16-cell-blocked: [ceil(C/16)][P][16], pair p of cell c at
+           ((c / 16) * P + p) * 16 + c % 16 (coag_rates_blocked, f32 = 1);
+   BLK64 : double, the same 16-cell-blocked order (coag_rates_blocked, f32 = 0).
+   A blocked array holds ceil(C/16) * 16 * P values; the padding cells of the
+   last block are read and must be finite (coag_rates_blocked writes zeros). */
+enum { COAG_RATES_CP64 = 0, COAG_RATES_BLK32 = 1, COAG_RATES_BLK64 = 2 };
+
 /* Mass grid and collision-outcome parameters (Sec. 5).  HOST arrays, copied
    by coag_create.  m strictly increasing; m_edge[k] < m[k] < m_edge[k+1]
    (bin edges, used by the fragment distribution eq. `Nijk`); s = grain radius
@@ -100,12 +109,12 @@ typedef struct {
    sub-steps per cell per call (ADAPTIVE), and the row length of h_log.
    prec: COAG_PREC_*.  renorm: non-zero rescales each cell's state after the
    call so that its total mass equals the total at entry (COAG_PREC_SPLIT_BF16
-   always does).  rates_f32: 1 if the Kc, Kf handed to coag_step are float
-   arrays in the 16-cell-blocked layout of coag_rates_f32
-   (COAG_PREC_SPLIT_BF16 only), 0 for double [C][P]. */
+   always does).  rates_layout: COAG_RATES_* of the Kc, Kf handed to
+   coag_step; BLK32 with COAG_PREC_SPLIT_BF16 only, BLK64 with COAG_PREC_FP64
+   only. */
 typedef struct {
     double rtol, atol_rel, h_min_rel;
-    int32_t max_sub, mode, prec, renorm, rates_f32;
+    int32_t max_sub, mode, prec, renorm, rates_layout;
 } coag_tol;
 
 /* ------------------------------------------------------------------------- */
@@ -148,14 +157,16 @@ const char *coag_last_error(const coag_ctx *ctx);
 int coag_rates(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
                const double *v_frag, double *Kc, double *Kf, void *stream);
 
-/* The same rates rounded to FP32, for the split-BF16 step (coag_tol.rates_f32
-   = 1), which then streams half the bytes per right-hand side, in whole
-   64-byte runs.  Layout: 16-cell blocks, [ceil(C/16)][P][16] floats, the rate
-   of cell c and pair p at ((c / 16) * P + p) * 16 + c % 16; Kc, Kf DEVICE out,
-   each ceil(C/16) * 16 * P floats, caller-owned; the padding cells of the last
-   block are written as zeros.  Errors as coag_rates. */
-int coag_rates_f32(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
-                   const double *v_frag, float *Kc, float *Kf, void *stream);
+/* The same rates in the 16-cell-blocked layout (COAG_RATES_BLK32 / BLK64
+   above): f32 = 1 rounds them to float, for the split-BF16 step, which then
+   streams half the bytes per right-hand side; f32 = 0 keeps double, for the
+   batched FP64 step.  Either way the 16 cells of a pair are one contiguous run
+   (64 or 128 bytes), so the batched step reads whole cache lines with no
+   reordering of its own.  Kc, Kf DEVICE out, ceil(C/16) * 16 * P elements
+   each, caller-owned; the padding cells of the last block are written as
+   zeros.  Errors as coag_rates, and COAG_EINVAL for f32 not 0 or 1. */
+int coag_rates_blocked(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
+                       const double *v_frag, int32_t f32, void *Kc, void *Kf, void *stream);
 
 /* Right-hand side of eq. `smol` for C cells:
      drho_k = sum_{i, j<=i} n_i n_j [Kc (m_i+m_j) C_ijk + Kf (m_rem R_ijk + m_frag F_ijk)]
@@ -178,9 +189,9 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
    a clipped accepted step leaves h unchanged.  FIXED: nsub[c] equal steps of
    dt/nsub[c].  REPLAY: nsub[c] steps of the sizes h_log[c][0..nsub[c]).
      rho     [C][N]        DEVICE in/out
-     Kc, Kf  [C][P]        DEVICE in (from coag_rates, or any kernel): double; or,
-                           when tol->rates_f32 = 1, float in the 16-cell-blocked
-                           layout of coag_rates_f32
+     Kc, Kf                DEVICE in, in tol->rates_layout: double [C][P] (from
+                           coag_rates, or any kernel), or 16-cell-blocked float or
+                           double (from coag_rates_blocked)
      h       [C]           DEVICE in/out (ADAPTIVE): h <= 0 on entry starts with dt;
                            on exit the controller's next (unclipped) step size
      nsub    [C] int32     DEVICE out (ADAPTIVE: accepted steps) or in (FIXED, REPLAY)
@@ -200,7 +211,9 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
        update and the per-cell mass bookkeeping stay in FP64.  Needs the same
        grid conditions (else COAG_ENOTSUP).
    Errors: COAG_EINVAL (null pointer, C < 0, dt <= 0, rtol <= 0, max_sub < 1,
-   unknown mode or precision, rates_f32 without split precision), COAG_ENOTSUP,
+   unknown mode, precision or rates layout, a layout the precision does not
+   take), COAG_ENOTSUP (split precision or blocked rates on a grid the batched
+   step does not cover; blocked FP64 rates with COAG_STEP_KERNEL=cell),
    COAG_ENOMEM. */
 int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void *Kf,
               double dt, double *h, const coag_tol *tol, int32_t *nsub, int32_t *nrej,

@@ -20,6 +20,7 @@ CELL_OK, CELL_HMIN, CELL_MAXSUB, CELL_NONFINITE = 0, 1, 2, 3
 SPLIT_MASS, SPLIT_NUMBER = 0, 1
 PREC_FP64, PREC_SPLIT_BF16 = 0, 1
 ADAPTIVE, FIXED, REPLAY = 0, 1, 2
+RATES_CP64, RATES_BLK32, RATES_BLK64 = 0, 1, 2
 
 _dp = ct.POINTER(ct.c_double)
 _vp = ct.c_void_p
@@ -37,7 +38,7 @@ class Cells(ct.Structure):
 class Tol(ct.Structure):
     _fields_ = [("rtol", ct.c_double), ("atol_rel", ct.c_double), ("h_min_rel", ct.c_double),
                 ("max_sub", ct.c_int32), ("mode", ct.c_int32), ("prec", ct.c_int32),
-                ("renorm", ct.c_int32), ("rates_f32", ct.c_int32)]
+                ("renorm", ct.c_int32), ("rates_layout", ct.c_int32)]
 
 
 class CoagError(RuntimeError):
@@ -66,7 +67,7 @@ def load():
         "coag_destroy": (None, [_vp]),
         "coag_last_error": (ct.c_char_p, [_vp]),
         "coag_rates": (ct.c_int, [_vp, i64, P(Cells), _vp, _vp, _vp, _vp, _vp]),
-        "coag_rates_f32": (ct.c_int, [_vp, i64, P(Cells), _vp, _vp, _vp, _vp, _vp]),
+        "coag_rates_blocked": (ct.c_int, [_vp, i64, P(Cells), _vp, _vp, i32, _vp, _vp, _vp]),
         "coag_rhs": (ct.c_int, [_vp, i64, _vp, _vp, _vp, _vp, _vp]),
         "coag_step": (ct.c_int, [_vp, i64, _vp, _vp, _vp, ct.c_double, _vp, P(Tol), _vp, _vp,
                                  _vp, _vp, _vp]),

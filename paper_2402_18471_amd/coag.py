@@ -1,5 +1,5 @@
 """Python face of libcoag with the C ABI's names (coag_mass_grid, coag_create,
-coag_rates, coag_rates_f32, coag_rhs, coag_step, coag_step_backward).
+coag_rates, coag_rates_blocked, coag_rhs, coag_step, coag_step_backward).
 
 Tensors are torch CUDA (HIP) tensors, float64 (int32 for counters), contiguous;
 torch supplies device memory and the current stream, nothing else.
@@ -96,23 +96,25 @@ class CoagContext:
         return Kc, Kf
 
     def blocked_shape(self, C):
-        """Shape of the 16-cell-blocked FP32 rates of C cells: the rate of
-        cell c, pair p at [c // 16, p, c % 16]."""
+        """Shape of the 16-cell-blocked rates of C cells: the rate of cell c,
+        pair p at [c // 16, p, c % 16]."""
         return ((C + 15) // 16, self.P, 16)
 
-    def coag_rates_f32(self, cells, v_dust, v_frag, Kc=None, Kf=None):
-        """The rates rounded to float32, for split-precision steps, in the
-        16-cell-blocked layout (blocked_shape(C))."""
+    def coag_rates_blocked(self, cells, v_dust, v_frag, dtype=torch.float32, Kc=None, Kf=None):
+        """The rates in the 16-cell-blocked layout (blocked_shape(C)), float32
+        (for split-precision steps) or float64 (for the batched FP64 step)."""
+        if dtype not in (torch.float32, torch.float64):
+            raise TypeError("dtype must be torch.float32 or torch.float64")
         C = int(v_frag.shape[0])
         cs, keep = self._cells(cells, C)
         _dev(v_dust, shape=(C, self.N, 3), name="v_dust")
         _dev(v_frag, shape=(C,), name="v_frag")
-        dev = v_frag.device
-        f32, shp = torch.float32, self.blocked_shape(C)
-        Kc = torch.empty(shp, dtype=f32, device=dev) if Kc is None else _dev(Kc, f32, shp, "Kc")
-        Kf = torch.empty(shp, dtype=f32, device=dev) if Kf is None else _dev(Kf, f32, shp, "Kf")
-        self._check(self._lib.coag_rates_f32(self._h, C, ct.byref(cs), _ptr(v_dust), _ptr(v_frag),
-                                             _ptr(Kc), _ptr(Kf), _stream()))
+        dev, shp = v_frag.device, self.blocked_shape(C)
+        Kc = torch.empty(shp, dtype=dtype, device=dev) if Kc is None else _dev(Kc, dtype, shp, "Kc")
+        Kf = torch.empty(shp, dtype=dtype, device=dev) if Kf is None else _dev(Kf, dtype, shp, "Kf")
+        self._check(self._lib.coag_rates_blocked(self._h, C, ct.byref(cs), _ptr(v_dust), _ptr(v_frag),
+                                                 1 if dtype == torch.float32 else 0,
+                                                 _ptr(Kc), _ptr(Kf), _stream()))
         return Kc, Kf
 
     def coag_rhs(self, rho, Kc, Kf, out=None):
@@ -128,14 +130,17 @@ class CoagContext:
                   atol_rel=1e-10, h_min_rel=1e-12, max_sub=10000, renorm=False, nsub=None,
                   h_log=None, log=True):
         """Advances rho (in place) by dt; returns dict(rho, h, nsub, nrej, h_log, status).
-        Kc, Kf: float64 [C][P] from coag_rates, or float32 in the blocked
-        layout of coag_rates_f32 (split precision only)."""
+        Kc, Kf: float64 [C][P] from coag_rates, or the 16-cell-blocked rates
+        of coag_rates_blocked (float32: split precision only; float64: FP64
+        only)."""
         C = int(rho.shape[0])
         dev = rho.device
         _dev(rho, shape=(C, self.N), name="rho")
-        rates_f32 = Kc.dtype == torch.float32
-        rdt = torch.float32 if rates_f32 else torch.float64
-        shp = self.blocked_shape(C) if rates_f32 else (C, self.P)
+        if Kc.dim() == 3:
+            layout = L.RATES_BLK32 if Kc.dtype == torch.float32 else L.RATES_BLK64
+            rdt, shp = Kc.dtype, self.blocked_shape(C)
+        else:
+            layout, rdt, shp = L.RATES_CP64, torch.float64, (C, self.P)
         _dev(Kc, dtype=rdt, shape=shp, name="Kc")
         _dev(Kf, dtype=rdt, shape=shp, name="Kf")
         if h is None:
@@ -154,8 +159,7 @@ class CoagContext:
             _dev(h_log, shape=(C, max_sub), name="h_log")
         nrej = torch.zeros(C, dtype=torch.int32, device=dev)
         status = torch.zeros(C, dtype=torch.int32, device=dev)
-        tol = L.Tol(rtol, atol_rel, h_min_rel, max_sub, mode, prec, 1 if renorm else 0,
-                    1 if rates_f32 else 0)
+        tol = L.Tol(rtol, atol_rel, h_min_rel, max_sub, mode, prec, 1 if renorm else 0, layout)
         self._check(self._lib.coag_step(self._h, C, _ptr(rho), _ptr(Kc), _ptr(Kf), float(dt),
                                         _ptr(h), ct.byref(tol), _ptr(nsub), _ptr(nrej),
                                         _ptr(h_log), _ptr(status), _stream()))

@@ -235,18 +235,19 @@ int coag_rates(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *
     return COAG_OK;
 }
 
-int coag_rates_f32(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
-                   const double *v_frag, float *Kc, float *Kf, void *stream) {
-    if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_rates_f32: ctx is NULL");
+int coag_rates_blocked(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
+                       const double *v_frag, int32_t f32, void *Kc, void *Kf, void *stream) {
+    if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_rates_blocked: ctx is NULL");
     if (C < 0 || C > 0x7fffffff)
-        return fail(ctx, COAG_EINVAL, "coag_rates_f32: bad C = %lld", (long long)C);
+        return fail(ctx, COAG_EINVAL, "coag_rates_blocked: bad C = %lld", (long long)C);
+    if (f32 != 0 && f32 != 1) return fail(ctx, COAG_EINVAL, "coag_rates_blocked: f32 must be 0 or 1");
     if (C == 0) return COAG_OK;
     if (int r = check_cells(ctx, cells)) return r;
     if (!v_dust || !v_frag || !Kc || !Kf)
-        return fail(ctx, COAG_EINVAL, "coag_rates_f32: NULL array");
+        return fail(ctx, COAG_EINVAL, "coag_rates_blocked: NULL array");
     if (int r = set_device(ctx)) return r;
-    HIP_TRY(ctx, launch_rates_f32(ctx->T, C, cell_arrays(cells), v_dust, v_frag, Kc, Kf,
-                                  (hipStream_t)stream));
+    HIP_TRY(ctx, launch_rates_blocked(ctx->T, C, cell_arrays(cells), v_dust, v_frag, f32, Kc, Kf,
+                                      (hipStream_t)stream));
     return COAG_OK;
 }
 
@@ -278,14 +279,22 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void 
     if (tol->prec != COAG_PREC_FP64 && tol->prec != COAG_PREC_SPLIT_BF16)
         return fail(ctx, COAG_EINVAL, "coag_step: unknown precision %d", tol->prec);
     if (tol->max_sub < 1) return fail(ctx, COAG_EINVAL, "coag_step: max_sub must be >= 1");
-    if (tol->rates_f32 != 0 && tol->rates_f32 != 1)
-        return fail(ctx, COAG_EINVAL, "coag_step: rates_f32 must be 0 or 1");
-    if (tol->rates_f32 && tol->prec != COAG_PREC_SPLIT_BF16)
+    const int layout = tol->rates_layout;
+    if (layout < COAG_RATES_CP64 || layout > COAG_RATES_BLK64)
+        return fail(ctx, COAG_EINVAL, "coag_step: unknown rates_layout %d", layout);
+    if (layout == COAG_RATES_BLK32 && tol->prec != COAG_PREC_SPLIT_BF16)
         return fail(ctx, COAG_EINVAL, "coag_step: FP32 rates need COAG_PREC_SPLIT_BF16");
-    if (tol->prec == COAG_PREC_SPLIT_BF16 && !batch_available(ctx->T, ctx->B))
+    if (layout == COAG_RATES_BLK64 && tol->prec != COAG_PREC_FP64)
+        return fail(ctx, COAG_EINVAL, "coag_step: blocked FP64 rates need COAG_PREC_FP64");
+    if ((tol->prec == COAG_PREC_SPLIT_BF16 || layout != COAG_RATES_CP64) &&
+        !batch_available(ctx->T, ctx->B))
         return fail(ctx, COAG_ENOTSUP,
-                    "coag_step: the split-BF16 step needs N >= 16 bins whose products of each "
-                    "row fit a 16-bin window, and N <= 400");
+                    "coag_step: the split-BF16 step and blocked rates need N >= 16 bins whose "
+                    "products of each row fit a 16-bin window, and N <= 400");
+    if (layout == COAG_RATES_BLK64 && !ctx->batch_fp64)
+        return fail(ctx, COAG_ENOTSUP,
+                    "coag_step: blocked FP64 rates need the batched step "
+                    "(COAG_STEP_KERNEL=cell selected the per-cell one)");
     if (tol->mode == COAG_ADAPTIVE) {
         if (!h && C > 0) return fail(ctx, COAG_EINVAL, "coag_step: h is required in ADAPTIVE mode");
         if (!(tol->rtol > 0.0) || !(tol->atol_rel >= 0.0) || !(tol->h_min_rel >= 0.0))
@@ -313,8 +322,8 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void 
     a.h_log = h_log;
     const bool split = tol->prec == COAG_PREC_SPLIT_BF16;
     if (split || (ctx->batch_fp64 && batch_available(ctx->T, ctx->B))) {
-        if (int r = ensure_ws(ctx, batch_ws_bytes(ctx->N, C, split ? 1 : 0))) return r;
-        HIP_TRY(ctx, launch_step_batch(ctx->T, ctx->B, C, a, split ? 1 : 0, tol->rates_f32,
+        if (int r = ensure_ws(ctx, batch_ws_bytes(ctx->N, C, split ? 1 : 0, layout))) return r;
+        HIP_TRY(ctx, launch_step_batch(ctx->T, ctx->B, C, a, split ? 1 : 0, layout,
                                        (double *)ctx->ws, (hipStream_t)stream));
     } else if (reg_path_available(ctx->N)) {
         HIP_TRY(ctx, launch_step2(ctx->T, C, a, (hipStream_t)stream));

@@ -38,11 +38,13 @@ hipError_t build_batch_tables(const Tables &T, void *mem, BatchTables *B);
 // whether the batched step runs for this context (window fit, LDS size)
 bool batch_available(const Tables &T, const BatchTables &B);
 // workspace of a batched step: four slopes and the candidate state per cell,
-// and (FP64 form, prec 0) the rates of every batch reordered pair-major with
-// the cells innermost
-size_t batch_ws_bytes(int N, long C, int prec);
-// prec: 0 = FP64 MFMA, 1 = split BF16; rates_f32: Kc / Kf are float arrays
+// and (FP64 form from [C][P] rates) the rates of every batch reordered
+// pair-major with the cells innermost
+size_t batch_ws_bytes(int N, long C, int prec, int layout);
+// prec: 0 = FP64 MFMA, 1 = split BF16.  layout of Kc / Kf: 0 = double [C][P],
+// 1 = float 16-cell-blocked (split only), 2 = double 16-cell-blocked (FP64
+// only); hipErrorNotSupported for other combinations
 hipError_t launch_step_batch(const Tables &T, const BatchTables &B, long C, const StepArgs &a,
-                             int prec, int rates_f32, double *ws, hipStream_t st);
+                             int prec, int layout, double *ws, hipStream_t st);
 
 }  // namespace coag

@@ -92,7 +92,11 @@ __device__ __forceinline__ double frag_mass(double mi, double mj, double chi, bo
     return (mi + mj) - mrem;
 }
 
-constexpr int kRing = 2;     // chunks of rates in flight per wave
+// chunks of rates in flight per wave: the FP64 form has the registers for a
+// deeper ring (one 8-wave workgroup per CU either way)
+constexpr int kRing64 = 4, kRing16 = 2;
+static_assert(kRing64 % 2 == 0 && kRing16 % 2 == 0,
+              "the D operands alternate between two register sets by chunk parity");
 
 // ---------------------------------------------------------------------------
 // tables
@@ -161,7 +165,7 @@ __global__ void k_batch_b(Tables T, int NC, const int *crow, const int *crow_c, 
     for (int s = 0; s < 8; ++s)
         b64[((long)ch * 8 + s) * 64 + lane] = d_entry(T, i, 16 * q + 4 * g + (s & 3), s >> 2, bin);
     // BF16 operand (chunks in the split form's order): K rows 8g + e <-> pair
-    // 16q + 8 (g % 2) + e, kind g / 2
+    // 16q + 4g + e % 4, kind e / 4 (both kinds of four pairs in one lane)
     i = crow_c[ch] & 0xffff;
     q = crow_c[ch] >> 16;
     bin = wb[i] + (lane & 15);
@@ -170,7 +174,7 @@ __global__ void k_batch_b(Tables T, int NC, const int *crow, const int *crow_c, 
         uint4 u;
     } L0, L1, L2;
     for (int e = 0; e < 8; ++e) {
-        const Limbs L = split3((float)d_entry(T, i, 16 * q + 8 * (g & 1) + e, g >> 1, bin));
+        const Limbs L = split3((float)d_entry(T, i, 16 * q + 4 * g + (e & 3), e >> 2, bin));
         L0.h[e] = L.a0;
         L1.h[e] = L.a1;
         L2.h[e] = L.a2;
@@ -201,7 +205,7 @@ __device__ __forceinline__ double wave_min_d(double v) {
     return v;
 }
 
-template <int PREC, typename RT>
+template <int PREC, typename RT, bool BLK>
 __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B, StepArgs a,
                                                         long C, double *ws, RT *wk) {
     extern __shared__ double lds[];
@@ -209,9 +213,9 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
     const long P = T.P;
     const long cell0 = (long)blockIdx.x * kBC;
     double *nv = lds, *net = lds + kBC * N, *phi = lds + 2 * kBC * N, *mk = lds + 3 * kBC * N;
-    int *fcol = (int *)(mk + N), *frow = fcol + N;
-    float *nf = (float *)(frow + N);              // split form: [16][N] n_k / max_k n_k
-    Ctl *ctl = (Ctl *)(lds + (3 * kBC + 2 + kBC / 2) * N);
+    int *fcol = (int *)(mk + N), *frow = fcol + N, *wbl = frow + N;
+    float *nf = (float *)(fcol + 4 * N);          // split form: [16][N] n_k / max_k n_k
+    Ctl *ctl = (Ctl *)(lds + (3 * kBC + 3 + kBC / 2) * N);
     int *flag = (int *)(ctl + kBC);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -219,6 +223,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         mk[k] = T.m[k];
         fcol[k] = T.fcol[k];
         frow[k] = T.frow[k];
+        wbl[k] = B.wb[k];
     }
     const bool adaptive = a.mode == 0;
     const double dt = a.dt;
@@ -233,7 +238,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
     // layout that coag_rates_f32 writes (whole 64-byte runs per pair), and FP64
     // rates as [C][P].
     RT *const kb = wk + (long)blockIdx.x * P * 2 * kBC;
-    if (PREC == 0) {
+    if (PREC == 0 && !BLK) {
         RT *tile = (RT *)lds;
         const int cap = (int)((3 * kBC * N * sizeof(double)) / (2 * kBC * sizeof(RT))) - 1;
         const int TP = cap < 128 ? cap : 128, TS = TP + 1;
@@ -341,7 +346,10 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
     // gain tile of a row accumulates over the row's chunks and is deposited
     // when the row changes; the loss of the lighter grain and the fragment mass
     // are deposited per pair.  The rates, the one stream from HBM, are loaded
-    // kRing chunks ahead into a register ring, the D operands one chunk ahead.
+    // kRing64 chunks ahead into a register ring, the D operands one chunk ahead.
+    // Every chunk issues the same loads in the same order, past the wave's
+    // last chunk repeating it, so that they are unconditional and each operand
+    // is waited for only when it is used.
     auto contract64 = [&]() {
         const int cl = lane & 15, g = lane >> 4;
         const int NC = B.NC;
@@ -363,26 +371,25 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         // accumulator layout of v_mfma_f64_16x16x4f64: lane l, register r ->
         // row (cell) l / 16 + 4 r, column (bin) l % 16
         auto flush = [&](int i) {
-            const int bin = B.wb[i] + cl;
+            const int bin = wbl[i] + cl;
 #pragma unroll
             for (int r = 0; r < 4; ++r) atomicAdd(&net[(g + 4 * r) * N + bin], acc64[r]);
         };
-        auto column = [&](int i, int jc, double rsum, double rf) {
-            atomicAdd(&netc[jc], -mk[jc] * rsum);
-            bool crater;
-            const double fm = frag_mass(mk[i], mk[jc], chi, crater);
-            atomicAdd(&phic[crater ? fcol[jc] : frow[i]], fm * rf);
-        };
+        // the batch's rates: reordered in the workspace ([P][kind][16]), or the
+        // caller's 16-cell-blocked arrays ([P][16] per kind)
+        const RT *kcb = BLK ? (const RT *)a.Kc + cell0 * P : kb;
+        const RT *kfb = BLK ? (const RT *)a.Kf + cell0 * P : kb + kBC;
+        constexpr long kps = BLK ? kBC : 2 * kBC;
         // lane (cell, g): pairs 16q + 4g + s, s = 0..3, both kinds
-        double rkc[kRing][4], rkf[kRing][4], bb[2][8];
+        double rkc[kRing64][4], rkf[kRing64][4], bb[2][8];
         auto load_k = [&](int i, int q, double (&kc)[4], double (&kf)[4]) {
             const long prow = (long)i * (i + 1) / 2;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int j = 16 * q + 4 * g + s;
-                const RT *kp = kb + (prow + (j <= i ? j : i)) * 2 * kBC + cl;
-                kc[s] = (double)kp[0];
-                kf[s] = (double)kp[kBC];
+                const long o = (prow + (j <= i ? j : i)) * kps + cl;
+                kc[s] = (double)kcb[o];
+                kf[s] = (double)kfb[o];
             }
         };
         auto load_b = [&](int ch, double (&b)[8]) {
@@ -390,52 +397,79 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
 #pragma unroll
             for (int s = 0; s < 8; ++s) b[s] = bt[s * 64];
         };
-#pragma unroll
-        for (int u = 0; u < kRing; ++u)
-            if (c0 + u < c1) {
-                load_k(ri, rq, rkc[u], rkf[u]);
-                advance(ri, rq);
+        int rleft = c1 - c0;                        // chunks whose rates are still to load
+        auto next_k = [&](double (&kc)[4], double (&kf)[4]) {
+            load_k(ri, rq, kc, kf);
+            if (--rleft > 0) advance(ri, rq);
+        };
+        // the heavier grain's values, per row
+        double ni = nrow[cur], mi = mk[cur];
+        int fri = frow[cur];
+        // One chunk.  The lane's four pairs read all their LDS operands first
+        // and deposit their column terms (loss of the lighter grain, fragment
+        // mass at its top bin) last, so that no read waits behind an atomic.
+        auto step = [&](int ch, int u) {
+            const int i = ci, q = cq;
+            advance(ci, cq);
+            load_b(ch + 1 < c1 ? ch + 1 : ch, bb[(u + 1) & 1]);
+            if (i != cur) {
+                flush(cur);
+                cur = i;
+                acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
+                ni = nrow[i];
+                mi = mk[i];
+                fri = frow[i];
             }
+            int jc[4], fc[4];
+            bool ok[4];
+            double nj[4], mj[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int j = 16 * q + 4 * g + s;
+                ok[s] = j <= i;
+                jc[s] = ok[s] ? j : i;
+                nj[s] = nrow[jc[s]];
+                mj[s] = mk[jc[s]];
+                fc[s] = fcol[jc[s]];
+            }
+            double rc[4], rf[4], loss[4], frag[4];
+            int fdst[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double nn = ok[s] ? ni * nj[s] : 0.0;
+                rc[s] = nn * rkc[u][s];
+                rf[s] = nn * rkf[u][s];
+                loss[s] = -mj[s] * (rc[s] + rf[s]);
+                bool crater;
+                frag[s] = frag_mass(mi, mj[s], chi, crater) * rf[s];
+                fdst[s] = crater ? fc[s] : fri;
+            }
+            const double(&b)[8] = bb[u & 1];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rc[s], b[s], acc64, 0, 0, 0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rf[s], b[4 + s], acc64, 0, 0, 0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                atomicAdd(&netc[jc[s]], loss[s]);
+                atomicAdd(&phic[fdst[s]], frag[s]);
+            }
+            next_k(rkc[u], rkf[u]);
+        };
+#pragma unroll
+        for (int u = 0; u < kRing64; ++u) next_k(rkc[u], rkf[u]);
         load_b(c0, bb[0]);
-        for (int base = c0; base < c1; base += kRing) {
+        const int cend = c0 + (c1 - c0) / kRing64 * kRing64;
+        int ch = c0;
+        for (; ch < cend; ch += kRing64) {
 #pragma unroll
-            for (int u = 0; u < kRing; ++u) {
-                const int ch = base + u;
-                if (ch < c1) {
-                    const int i = ci, q = cq;
-                    advance(ci, cq);
-                    if (ch + 1 < c1) load_b(ch + 1, bb[(u + 1) & 1]);
-                    if (i != cur) {
-                        flush(cur);
-                        cur = i;
-                        acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
-                    }
-                    const double ni = nrow[i];
-                    double rc[4], rf[4];
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const int j = 16 * q + 4 * g + s;
-                        const bool ok = j <= i;
-                        const int jc = ok ? j : i;
-                        const double nn = ok ? ni * nrow[jc] : 0.0;
-                        rc[s] = nn * rkc[u][s];
-                        rf[s] = nn * rkf[u][s];
-                        column(i, jc, rc[s] + rf[s], rf[s]);
-                    }
-                    const double(&b)[8] = bb[u & 1];
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rc[s], b[s], acc64, 0, 0, 0);
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rf[s], b[4 + s], acc64, 0, 0, 0);
-                    if (ch + kRing < c1) {
-                        load_k(ri, rq, rkc[u], rkf[u]);
-                        advance(ri, rq);
-                    }
-                }
-            }
+            for (int u = 0; u < kRing64; ++u) step(ch + u, u);
         }
+#pragma unroll
+        for (int u = 0; u < kRing64 - 1; ++u)
+            if (ch + u < c1) step(ch + u, u);
         flush(cur);
     };
 
@@ -446,7 +480,8 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
     // top bin of j) are summed in registers and deposited when the column
     // block changes.  The FP32 gain tile of a chunk (row i's window) is scaled
     // back and deposited while the next chunk's products run.  Rates are
-    // loaded kRing chunks ahead into a register ring, D operands one ahead.
+    // loaded kRing16 chunks ahead into a register ring, D operands one ahead,
+    // unconditionally as in the FP64 form.
     auto contract16 = [&]() {
         const int cl = lane & 15, g = lane >> 4;
         const int NC = B.NC;
@@ -471,7 +506,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         // accumulator layout of v_mfma_f32_16x16x32_bf16: lane l, register r ->
         // row (cell) 4 (l / 16) + r, column (bin) l % 16
         auto flush_tile = [&](int i, int t) {
-            const int bin = B.wb[i] + cl;
+            const int bin = wbl[i] + cl;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int c = 4 * g + r;
@@ -480,11 +515,10 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             }
             acc32[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         };
-        // this lane's lighter grains in column block q, and their running sums
-        // (fragments only on the lanes that hold fragmenting rates)
-        constexpr int NJ = 8;
-        const bool fraglane = (g >> 1) != 0;
-        auto jof = [&](int q, int u) { return 16 * q + 8 * (g & 1) + u; };
+        // this lane's lighter grains in column block q (both kinds of four
+        // pairs), and their running sums
+        constexpr int NJ = 4;
+        auto jof = [&](int q, int u) { return 16 * q + 4 * g + u; };
         double colsum[NJ], fragsum[NJ];
 #pragma unroll
         for (int u = 0; u < NJ; ++u) colsum[u] = fragsum[u] = 0.0;
@@ -494,40 +528,32 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                 const int j = jof(q, u);
                 if (j < N) {
                     atomicAdd(&netc[j], -mk[j] * colsum[u]);
-                    if (fraglane) atomicAdd(&phic[fcol[j]], fragsum[u]);
+                    atomicAdd(&phic[fcol[j]], fragsum[u]);
                 }
                 colsum[u] = 0.0;
                 fragsum[u] = 0.0;
             }
         };
-        // one pair's column terms: rate sum, and fragments (crater: summed for
-        // the block; destroyed target: straight to the top bin of m_i)
-        auto pair_terms = [&](int u, int i, int jc, bool ok, double rsum, double rf) {
-            colsum[u] += rsum;
-            if (fraglane) {
-                bool crater;
-                const double fr = frag_mass(mk[i], mk[jc], chi, crater) * rf;
-                fragsum[u] += crater ? fr : 0.0;
-                if (ok && !crater) atomicAdd(&phic[frow[i]], fr);
-            }
-        };
         int colq = cq, prev = -1;
-        // lane (cell, g): pairs 16q + 8 (g % 2) + e, e = 0..7, kind g / 2
-        const int kind = g >> 1;
+        // lane (cell, g): pairs 16q + 4g + s, s = 0..3, Kc in k[s], Kf in
+        // k[4 + s] (the K rows of the MFMA operands)
         // FP32 rates: pair p of the batch's cell cl at p * 16 + cl (padding
         // cells hold zeros); FP64 rates: [C][P], cells past C read cell C - 1
-        constexpr bool blk = sizeof(RT) == 4;
+        constexpr bool blk = BLK;
         constexpr long ks = blk ? 16 : 1;
         const long cb = cell0 + cl < C ? cell0 + cl : C - 1;
-        const RT *K = (const RT *)(kind ? a.Kf : a.Kc) + (blk ? cell0 * P + cl : cb * P);
-        RT rk[kRing][8];
+        const long kbase = blk ? cell0 * P + cl : cb * P;
+        const RT *Kc = (const RT *)a.Kc + kbase, *Kf = (const RT *)a.Kf + kbase;
+        RT rk[kRing16][8];
         uint4 bb[2][3];
         auto load_k = [&](int i, int q, RT (&k)[8]) {
             const long prow = (long)i * (i + 1) / 2;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int j = 16 * q + 8 * (g & 1) + e;
-                k[e] = K[(prow + (j <= i ? j : i)) * ks];
+            for (int s = 0; s < 4; ++s) {
+                const int j = 16 * q + 4 * g + s;
+                const long o = (prow + (j <= i ? j : i)) * ks;
+                k[s] = Kc[o];
+                k[4 + s] = Kf[o];
             }
         };
         auto load_b = [&](int ch, uint4 (&b)[3]) {
@@ -536,67 +562,78 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             b[1] = bt[64];
             b[2] = bt[128];
         };
-#pragma unroll
-        for (int u = 0; u < kRing; ++u)
-            if (c0 + u < c1) {
-                load_k(ri, rq, rk[u]);
-                advance(ri, rq);
+        int rleft = c1 - c0;                        // chunks whose rates are still to load
+        auto next_k = [&](RT (&k)[8]) {
+            load_k(ri, rq, k);
+            if (--rleft > 0) advance(ri, rq);
+        };
+        auto step = [&](int ch, int u) {
+            const int i = ci, q = cq;
+            advance(ci, cq);
+            load_b(ch + 1 < c1 ? ch + 1 : ch, bb[(u + 1) & 1]);
+            if (q != colq) {
+                flush_cols(colq);
+                colq = q;
             }
-        load_b(c0, bb[0]);
-        for (int base = c0; base < c1; base += kRing) {
+            // x = n_j K / max n (FP32, the MFMA operand); the FP64 rate of
+            // the pair for the column terms is (n_i max n) x.  Column terms:
+            // the rate sums, and fragments (crater: summed for the block;
+            // destroyed target: summed for the chunk, all at the top bin of
+            // m_i)
+            const double c64 = nrow[i] * nmax, mi = mk[i];
+            float x[8];
+            double dest = 0.0;
+            auto pairs = [&](bool full) {
 #pragma unroll
-            for (int u = 0; u < kRing; ++u) {
-                const int ch = base + u;
-                if (ch < c1) {
-                    const int i = ci, q = cq;
-                    advance(ci, cq);
-                    if (ch + 1 < c1) load_b(ch + 1, bb[(u + 1) & 1]);
-                    if (q != colq) {
-                        flush_cols(colq);
-                        colq = q;
-                    }
-                    // x = n_j K / max n (FP32, the MFMA operand); the FP64
-                    // rate of the pair for the column terms is (n_i max n) x
-                    const double c64 = nrow[i] * nmax;
-                    float x[8];
-                    auto pairs = [&](bool full) {
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const int j = 16 * q + 8 * (g & 1) + e;
-                            const bool ok = full || j <= i;
-                            const int jc = ok ? j : i;
-                            const float xe = nfr[jc] * (float)rk[u][e];
-                            x[e] = ok ? xe : 0.0f;
-                            const double r = c64 * (double)x[e];
-                            pair_terms(e, i, jc, ok, r, r);
-                        }
-                    };
-                    if (16 * q + 15 <= i) pairs(true);
-                    else pairs(false);
-                    const Limbs8 L = split3x8(x);
-                    union {
-                        uint4 u;
-                        bf16x8 v;
-                    } B0, B1, B2;
-                    B0.u = bb[u & 1][0];
-                    B1.u = bb[u & 1][1];
-                    B2.u = bb[u & 1][2];
-                    f32x4 &acc = acc32[u & 1];         // one chunk per FP32 accumulation
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B0.v, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B1.v, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B0.v, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B2.v, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B1.v, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a2, B0.v, acc, 0, 0, 0);
-                    if (prev >= 0) flush_tile(prev, (u + 1) & 1);
-                    prev = i;
-                    if (ch + kRing < c1) {
-                        load_k(ri, rq, rk[u]);
-                        advance(ri, rq);
-                    }
+                for (int s = 0; s < 4; ++s) {
+                    const int j = 16 * q + 4 * g + s;
+                    const bool ok = full || j <= i;
+                    const int jc = ok ? j : i;
+                    const float nj = nfr[jc];
+                    x[s] = ok ? nj * (float)rk[u][s] : 0.0f;
+                    x[4 + s] = ok ? nj * (float)rk[u][4 + s] : 0.0f;
+                    const double rc = c64 * (double)x[s], rf = c64 * (double)x[4 + s];
+                    colsum[s] += rc + rf;
+                    bool crater;
+                    const double fr = frag_mass(mi, mk[jc], chi, crater) * rf;
+                    fragsum[s] += crater ? fr : 0.0;
+                    dest += crater ? 0.0 : fr;
                 }
-            }
+            };
+            if (16 * q + 15 <= i) pairs(true);
+            else pairs(false);
+            atomicAdd(&phic[frow[i]], dest);
+            const Limbs8 L = split3x8(x);
+            union {
+                uint4 u;
+                bf16x8 v;
+            } B0, B1, B2;
+            B0.u = bb[u & 1][0];
+            B1.u = bb[u & 1][1];
+            B2.u = bb[u & 1][2];
+            f32x4 &acc = acc32[u & 1];                 // one chunk per FP32 accumulation
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B0.v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B1.v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B0.v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B2.v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B1.v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a2, B0.v, acc, 0, 0, 0);
+            if (prev >= 0) flush_tile(prev, (u + 1) & 1);
+            prev = i;
+            next_k(rk[u]);
+        };
+#pragma unroll
+        for (int u = 0; u < kRing16; ++u) next_k(rk[u]);
+        load_b(c0, bb[0]);
+        const int cend = c0 + (c1 - c0) / kRing16 * kRing16;
+        int ch = c0;
+        for (; ch < cend; ch += kRing16) {
+#pragma unroll
+            for (int u = 0; u < kRing16; ++u) step(ch + u, u);
         }
+#pragma unroll
+        for (int u = 0; u < kRing16 - 1; ++u)
+            if (ch + u < c1) step(ch + u, u);
         flush_tile(prev, (c1 - 1 - c0) & 1);        // the last chunk's tile
         flush_cols(colq);
     };
@@ -766,7 +803,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
 }
 
 size_t batch_lds_bytes(int N) {
-    return (size_t)(3 * kBC + 2 + kBC / 2) * N * sizeof(double) + kBC * sizeof(Ctl) + 64;
+    return (size_t)(3 * kBC + 3 + kBC / 2) * N * sizeof(double) + kBC * sizeof(Ctl) + 64;
 }
 
 template <typename K>
@@ -840,32 +877,30 @@ static size_t slope_bytes(int N, long C) {
     return ((size_t)nb * kBC * 5 * N * sizeof(double) + 255) & ~size_t(255);
 }
 
-size_t batch_ws_bytes(int N, long C, int prec) {
+size_t batch_ws_bytes(int N, long C, int prec, int layout) {
     const long nb = (C + kBC - 1) / kBC;
     const size_t P = (size_t)N * (N + 1) / 2;
-    return slope_bytes(N, C) + (prec == 0 ? (size_t)nb * P * 2 * kBC * sizeof(double) : 0);
+    const bool reorder = prec == 0 && layout == 0;
+    return slope_bytes(N, C) + (reorder ? (size_t)nb * P * 2 * kBC * sizeof(double) : 0);
 }
 
 hipError_t launch_step_batch(const Tables &T, const BatchTables &B, long C, const StepArgs &a,
-                             int prec, int rates_f32, double *ws, hipStream_t st) {
+                             int prec, int layout, double *ws, hipStream_t st) {
     if (C == 0) return hipSuccess;
     if (!batch_available(T, B)) return hipErrorNotSupported;
     const size_t bytes = batch_lds_bytes(T.N);
     const dim3 grid((unsigned)((C + kBC - 1) / kBC)), block(kBBlock);
-#define LAUNCH(PR, RT)                                                                       \
+#define LAUNCH(PR, RT, BL)                                                                   \
     do {                                                                                     \
-        if (hipError_t e = allow_lds_b(k_step_batch<PR, RT>, bytes)) return e;              \
-        hipLaunchKernelGGL((k_step_batch<PR, RT>), grid, block, bytes, st, T, B, a, C, ws,  \
-                           (RT *)((char *)ws + slope_bytes(T.N, C)));                        \
+        if (hipError_t e = allow_lds_b(k_step_batch<PR, RT, BL>, bytes)) return e;          \
+        hipLaunchKernelGGL((k_step_batch<PR, RT, BL>), grid, block, bytes, st, T, B, a, C,  \
+                           ws, (RT *)((char *)ws + slope_bytes(T.N, C)));                    \
     } while (0)
-    if (prec == 0) {
-        if (rates_f32) return hipErrorNotSupported;
-        LAUNCH(0, double);
-    } else if (rates_f32) {
-        LAUNCH(1, float);
-    } else {
-        LAUNCH(1, double);
-    }
+    if (prec == 0 && layout == 0) LAUNCH(0, double, false);
+    else if (prec == 0 && layout == 2) LAUNCH(0, double, true);
+    else if (prec == 1 && layout == 0) LAUNCH(1, double, false);
+    else if (prec == 1 && layout == 1) LAUNCH(1, float, true);
+    else return hipErrorNotSupported;
 #undef LAUNCH
     return hipGetLastError();
 }

@@ -285,10 +285,11 @@ __global__ __launch_bounds__(kRatesBlock) void k_rates(Tables T, CellArrays cell
     }
 }
 
-// FP32 pair rates in the 16-cell-blocked layout (rate of cell c, pair p at
+// Pair rates in the 16-cell-blocked layout (rate of cell c, pair p at
 // ((c / 16) P + p) 16 + c % 16; the padding cells of the last block get
-// zeros).  16 cells per workgroup; lane t works on cell t % 16 and pairs
-// t / 16 + 64 k, so that the 16 cells of a pair leave as one 64-byte run.
+// zeros), double or rounded to float.  16 cells per workgroup; lane t works on
+// cell t % 16 and pairs t / 16 + 64 k, so that the 16 cells of a pair leave as
+// one run (64 bytes in FP32, a 128-byte line in FP64).
 // Per-grain values in LDS as [value][bin][cell] (the lanes of a pair read 16
 // consecutive doubles).  TAB = 7 tabulates St, A, B, C and the velocity; for
 // grids whose 16 cells' values would not fit LDS otherwise, TAB = 6 leaves
@@ -297,11 +298,11 @@ __global__ __launch_bounds__(kRatesBlock) void k_rates(Tables T, CellArrays cell
 template <int TAB>
 static size_t rates_blk_lds_bytes(int N) { return (size_t)(16 * TAB + 2) * N * sizeof(double); }
 
-template <int TAB>
+template <int TAB, typename OT>
 __global__ __launch_bounds__(1024) void k_rates_blk(Tables T, CellArrays cells,
                                                     const double *__restrict__ v_dust,
                                                     const double *__restrict__ v_frag,
-                                                    float *__restrict__ Kc, float *__restrict__ Kf,
+                                                    OT *__restrict__ Kc, OT *__restrict__ Kf,
                                                     long C) {
     static_assert(TAB == 7 || TAB == 6 || TAB == 1, "tabulated values per grain");
     constexpr int VX = TAB - 3;                       // first velocity row (TAB >= 6)
@@ -363,12 +364,12 @@ __global__ __launch_bounds__(1024) void k_rates_blk(Tables T, CellArrays cells,
         g.s = sv[k];
         return g;
     };
-    float *kc = Kc + cell0 * P + cl, *kf = Kf + cell0 * P + cl;
+    OT *kc = Kc + cell0 * P + cl, *kf = Kf + cell0 * P + cl;
     uint32_t ijn = slot < P ? T.pij[slot] : 0u;
     for (int p = slot; p < P; p += 64) {
         const uint32_t ij = ijn;
         if (p + 64 < P) ijn = T.pij[p + 64];
-        float oc = 0.0f, of = 0.0f;
+        OT oc = (OT)0, of = (OT)0;
         if (live) {
             const int i = pair_i(ij), j = pair_j(ij);
             Grain gi = grain(i);
@@ -377,8 +378,8 @@ __global__ __launch_bounds__(1024) void k_rates_blk(Tables T, CellArrays cells,
             heavier_terms(r, gi, S);
             double c64, f64;
             pair_rates(r, gi, grain(j), i == j, c64, f64);
-            oc = (float)c64;
-            of = (float)f64;
+            oc = (OT)c64;
+            of = (OT)f64;
         }
         kc[(long)p * 16] = oc;
         kf[(long)p * 16] = of;
@@ -737,17 +738,17 @@ hipError_t launch_rates(const Tables &T, long C, const CellArrays &cells, const 
     return hipGetLastError();
 }
 
-hipError_t launch_rates_f32(const Tables &T, long C, const CellArrays &cells,
-                            const double *v_dust, const double *v_frag, float *Kc, float *Kf,
-                            hipStream_t st) {
-    if (C == 0) return hipSuccess;
+template <typename OT>
+static hipError_t launch_rates_blk(const Tables &T, long C, const CellArrays &cells,
+                                   const double *v_dust, const double *v_frag, OT *Kc, OT *Kf,
+                                   hipStream_t st) {
     const unsigned blocks = (unsigned)((C + 15) / 16);
     constexpr size_t kLds = 160 * 1024;
 #define RATES_BLK(TAB)                                                                            \
     {                                                                                             \
         const size_t bytes = rates_blk_lds_bytes<TAB>(T.N);                                       \
-        if (hipError_t e = allow_lds(k_rates_blk<TAB>, bytes)) return e;                          \
-        hipLaunchKernelGGL(k_rates_blk<TAB>, dim3(blocks), dim3(1024), bytes, st, T, cells,       \
+        if (hipError_t e = allow_lds(k_rates_blk<TAB, OT>, bytes)) return e;                      \
+        hipLaunchKernelGGL((k_rates_blk<TAB, OT>), dim3(blocks), dim3(1024), bytes, st, T, cells, \
                            v_dust, v_frag, Kc, Kf, C);                                            \
     }
     if (rates_blk_lds_bytes<7>(T.N) <= kLds) RATES_BLK(7)
@@ -755,6 +756,14 @@ hipError_t launch_rates_f32(const Tables &T, long C, const CellArrays &cells,
     else RATES_BLK(1)               // fits LDS for every N <= kMaxBins
 #undef RATES_BLK
     return hipGetLastError();
+}
+
+hipError_t launch_rates_blocked(const Tables &T, long C, const CellArrays &cells,
+                                const double *v_dust, const double *v_frag, int f32, void *Kc,
+                                void *Kf, hipStream_t st) {
+    if (C == 0) return hipSuccess;
+    if (f32) return launch_rates_blk(T, C, cells, v_dust, v_frag, (float *)Kc, (float *)Kf, st);
+    return launch_rates_blk(T, C, cells, v_dust, v_frag, (double *)Kc, (double *)Kf, st);
 }
 
 hipError_t launch_rhs(const Tables &T, long C, const double *rho, const double *Kc,

@@ -17,7 +17,7 @@ def test_library_exports_every_declared_symbol(L):
     lib = L.load()
     names = L.header_symbols()
     assert set(names) == {"coag_mass_grid", "coag_create", "coag_destroy", "coag_last_error",
-                          "coag_rates", "coag_rates_f32", "coag_rhs", "coag_step",
+                          "coag_rates", "coag_rates_blocked", "coag_rhs", "coag_step",
                           "coag_step_backward"}
     for n in names:
         assert hasattr(lib, n), n
@@ -80,6 +80,7 @@ def test_calls_reject_null_context(L):
     assert lib.coag_step(None, 1, None, None, None, 1.0, None, ct.byref(tol), None, None, None,
                          None, None) == L.COAG_EINVAL
     assert lib.coag_rates(None, 1, None, None, None, None, None, None) == L.COAG_EINVAL
+    assert lib.coag_rates_blocked(None, 1, None, None, None, 1, None, None, None) == L.COAG_EINVAL
     assert lib.coag_step_backward(None, 1, None, None, None, None, None, 1, None, None, None,
                                   None, None, 0, None) == L.COAG_EINVAL
     lib.coag_destroy(None)

@@ -1,4 +1,4 @@
-"""Split-BF16 step (COAG_PREC_SPLIT_BF16) and FP32 rates against the FP64 oracle.
+"""Split-BF16 step (COAG_PREC_SPLIT_BF16) and blocked FP32 rates against the FP64 oracle.
 
 The split arithmetic perturbs every right-hand side by a few 2^-24 of the
 gain terms of each bin (the gain contraction runs on three-limb BF16 products
@@ -73,7 +73,7 @@ RATE_CASES = CASES[:3] + [("disc64x32_n100", 13, 3), ("disc64x32_n100", 5, 7)]
 
 
 @pytest.mark.parametrize("case", RATE_CASES + [("disc64x32_n100", 5, 7, 320)])
-def test_rates_f32(O, case):
+def test_rates_blocked_f32(O, case):
     if len(case) == 4:
         from paper_2402_18471_amd import disc
         from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
@@ -86,7 +86,7 @@ def test_rates_f32(O, case):
     else:
         cfg, g, d, ctx, cells = _case(O, *case)
     C = cfg.n_cells
-    Kc, Kf = ctx.coag_rates_f32(cells, _t(d["v_dust"]), _t(d["v_frag"]))
+    Kc, Kf = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]))
     torch.cuda.synchronize()
     assert tuple(Kc.shape) == ((C + 15) // 16, ctx.P, 16)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
@@ -102,7 +102,7 @@ def test_split_step_replays_oracle_steps(O, case, rates):
     cfg, g, d, ctx, cells = _case(O, *case)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
     if rates == "f32":
-        Kc, Kf = ctx.coag_rates_f32(cells, _t(d["v_dust"]), _t(d["v_frag"]))
+        Kc, Kf = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]))
     else:
         Kc, Kf = _t(oKc), _t(oKf)
     for rho0, dt in ((d["rho"], d["dt"]), (d["rho"], 20 * d["dt"]),
@@ -124,7 +124,7 @@ def test_split_adaptive_replayed_by_oracle(O, case):
     """ADAPTIVE split step; the oracle replays its accepted steps."""
     cfg, g, d, ctx, cells = _case(O, *case)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
-    Kc, Kf = ctx.coag_rates_f32(cells, _t(d["v_dust"]), _t(d["v_frag"]))
+    Kc, Kf = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]))
     rho0, dt = d["rho"], 20 * d["dt"]
     r = ctx.coag_step(_t(rho0), Kc, Kf, dt, prec=1, max_sub=256)
     torch.cuda.synchronize()
@@ -146,7 +146,7 @@ def test_split_rejections_and_host_errors(O):
     from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
     cfg, g, d, ctx, cells = _case(O, "disc64x32_n100", 2, 2)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
-    Kc32, Kf32 = ctx.coag_rates_f32(cells, _t(d["v_dust"]), _t(d["v_frag"]))
+    Kc32, Kf32 = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]))
     rho = _t(d["rho"])
     before = rho.clone()
     with pytest.raises(L.CoagError) as e:       # FP32 rates with the FP64 step
