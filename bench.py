@@ -96,12 +96,69 @@ def parse():
                     help="FP64 step kernel (cell: one workgroup per cell)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--evolve", metavar="CONFIG",
+                    help="instead of the step benchmark: differentiable coagulation calls "
+                         "(torch.autograd, checkpointed) on CONFIG, forward and backward timed")
+    ap.add_argument("--evolve-calls", type=int, default=20)
+    ap.add_argument("--evolve-ckpt", type=int, default=20)
+    ap.add_argument("--evolve-prec", choices=("fp64", "split"), default="split")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_LOG"),
                     help="no GPU work: write the counter summary the roofline's traffic is read "
                          "from, from the counter_collection.csv files of a FETCH_SIZE and a "
                          "WRITE_SIZE rocprofv3 pass over 'bench.py --steps 1 --warmup 1 "
                          "--no-cpu-baseline --no-adjoint --calibrate-copy', and that run's output")
     return ap.parse_args()
+
+
+def evolve(args):
+    """Forward and backward time of n differentiable coagulation calls
+    (paper_2402_18471_amd.autograd.coag_evolve: ADAPTIVE, checkpoint every
+    ckpt calls; the backward recomputes each segment and runs the FP64
+    adjoint) on one disc, loss = sum over cells of the mass-weighted mean
+    ln s, and the device memory in use at the end of each pass."""
+    import torch
+    from paper_2402_18471_amd import disc
+    from paper_2402_18471_amd import _lib as L
+    from paper_2402_18471_amd.autograd import coag_evolve
+    from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
+    cfg = disc.CONFIGS[args.evolve]
+    m, me, s = coag_mass_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
+    d = disc.make_disc(cfg, s)
+    dev = "cuda:0"
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
+    cells = {k: t(v) for k, v in d["cells"].items()}
+    rho0 = t(d["rho"]).requires_grad_(True)
+    al = t(d["cells"]["alpha"]).requires_grad_(True)
+    vf = t(d["v_frag"]).requires_grad_(True)
+    lns = t(np.log(s))
+    prec = L.PREC_SPLIT_BF16 if args.evolve_prec == "split" else L.PREC_FP64
+    free0, total = torch.cuda.mem_get_info()
+    progress(f"evolve {cfg.name}: {args.evolve_calls} calls, {args.evolve_prec} forward")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = coag_evolve(ctx, rho0, al, vf, cells, t(d["v_dust"]), float(d["dt"]), args.evolve_calls,
+                      ckpt_every=args.evolve_ckpt, prec=prec, max_sub=64)
+    J = ((out * lns).sum(1) / out.sum(1)).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    used_fwd = (total - torch.cuda.mem_get_info()[0]) / 1e9
+    progress(f"forward {t1 - t0:.2f} s")
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    used_bwd = (total - torch.cuda.mem_get_info()[0]) / 1e9
+    progress(f"backward {t2 - t1:.2f} s")
+    g = [x.grad for x in (rho0, al, vf)]
+    print(json.dumps({
+        "workload": cfg.name, "cells": cfg.n_cells, "bins": cfg.n_bins, "calls": args.evolve_calls,
+        "ckpt_every": args.evolve_ckpt, "forward_precision": args.evolve_prec,
+        "adjoint_precision": "fp64", "forward_s": t1 - t0, "backward_s": t2 - t1,
+        "backward_over_forward": (t2 - t1) / (t1 - t0),
+        "device_memory_in_use_gb": {"before": (total - free0) / 1e9, "after_forward": used_fwd,
+                                    "after_backward": used_bwd},
+        "gradients_finite": bool(all(torch.isfinite(x).all() for x in g)),
+        "data": "synthetic disc, forward = coag_rates + ADAPTIVE coag_step per call"}), flush=True)
 
 
 def summarize_counters(fetch_csv, write_csv, bench_log):
@@ -331,6 +388,9 @@ def main():
     args = parse()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
+        return
+    if args.evolve:
+        evolve(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "

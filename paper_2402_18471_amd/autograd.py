@@ -9,7 +9,9 @@ segment is recomputed from its checkpoint with the recorded step sizes
 (REPLAY, so the step sequence is exactly the one the forward pass took) and
 the adjoint runs through its calls in reverse.  Gradients are returned for the
 initial density, alpha and v_frag (per cell); the other inputs are not
-differentiated.
+differentiated.  The adjoint is FP64: after a split-precision forward pass it
+differentiates the FP64 map along the split trajectory (the recomputation
+replays the split steps, the adjoint its own FP64 stages).
 """
 from __future__ import annotations
 
@@ -74,7 +76,8 @@ class CoagStep(torch.autograd.Function):
                                    nsub=ctx.nsubs[s], h_log=ctx.logs[s])
             for s in range(s1 - 1, s0 - 1, -1):
                 gi, ga, gv = coag.coag_step_backward(starts[s - s0], cells, v_dust, vf,
-                                                     ctx.logs[s], ctx.nsubs[s], g, prec=ctx.prec)
+                                                     ctx.logs[s], ctx.nsubs[s], g,
+                                                     prec=L.PREC_FP64)
                 g = gi
                 g_alpha += ga
                 g_vfrag += gv

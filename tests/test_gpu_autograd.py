@@ -48,18 +48,18 @@ def _per_cell_loss(rho, lns):
     return (rho * lns).sum(1) / rho.sum(1)
 
 
-def _run(ctx, d, rho0, alpha, vfrag, dt, ckpt=CKPT):
+def _run(ctx, d, rho0, alpha, vfrag, dt, ckpt=CKPT, prec=0):
     from paper_2402_18471_amd.autograd import coag_evolve
     cells = {k: _t(v) for k, v in d["cells"].items()}
     return coag_evolve(ctx, rho0, alpha, vfrag, cells, _t(d["v_dust"]), dt, N_CALLS,
-                       ckpt_every=ckpt, fixed_nsub=NSUB, max_sub=NSUB)
+                       ckpt_every=ckpt, fixed_nsub=NSUB, max_sub=NSUB, prec=prec)
 
 
-def _grads(ctx, d, rho, dt, lns, ckpt=CKPT):
+def _grads(ctx, d, rho, dt, lns, ckpt=CKPT, prec=0):
     rho0 = _t(rho).requires_grad_(True)
     alpha = _t(d["cells"]["alpha"]).requires_grad_(True)
     vfrag = _t(d["v_frag"]).requires_grad_(True)
-    out = _run(ctx, d, rho0, alpha, vfrag, dt, ckpt)
+    out = _run(ctx, d, rho0, alpha, vfrag, dt, ckpt, prec)
     J = _per_cell_loss(out, _t(lns)).sum()
     J.backward()
     torch.cuda.synchronize()
@@ -135,3 +135,16 @@ def test_checkpoint_interval_does_not_change_gradients(O):
     for x, y, z in zip(a[:3], b[:3], c[:3]):
         sc = np.abs(x).max()
         assert np.abs(x - y).max() <= 1e-12 * sc and np.abs(x - z).max() <= 1e-12 * sc
+
+
+def test_split_forward_takes_the_fp64_adjoint(O):
+    """A split-BF16 forward pass differentiates through the FP64 adjoint along
+    its own trajectory: states within the split bar of the FP64 forward, and
+    gradients within 1e-5 of the largest component of the FP64 forward's."""
+    g, d, rho, ctx, dt, lns = _setup(O)
+    a = _grads(ctx, d, rho, dt, lns)
+    b = _grads(ctx, d, rho, dt, lns, prec=1)
+    M = rho.sum(1, keepdims=True)
+    assert np.all(np.abs(b[3] - a[3]) <= 1e-6 * np.abs(a[3]) + 1e-18 * M)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.abs(x - y).max() <= 1e-5 * np.abs(x).max()
