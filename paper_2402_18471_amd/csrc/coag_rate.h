@@ -1,0 +1,219 @@
+// coag_rate.h -- the pair-rate arithmetic (Sec. 5, eqs. `kernel`, `vbrown`,
+// `OCVrel`, `p_frag`, `t_stop`) of the rate kernels (coag_kernels.hip): the
+// per-cell and per-grain terms, one pair's rates, and the writer of one
+// 16-cell block in the blocked layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "coag_device.h"
+#include "coag_launch.h"
+
+namespace coag {
+
+// ---------------------------------------------------------------------------
+// Pair rates.  Everything in the Ormel & Cuzzi expressions that depends on one
+// bin only is tabulated per cell in LDS first.  Stokes numbers grow
+// with grain size, so the heavier grain i of a pair is the one with the larger
+// Stokes number: St_1 = St_i, St* = clamp(y* St_i, Re^-1/2, 1) is a per-row
+// value, and per pair only (St_i - St_j) / (St_i + St_j) and
+// St_j^2 / (St* + St_j) remain to divide (plus v_frag / dv).
+//   A_k = St_k^2 / (1 + St_k),  B_k = St_k^2 / (St_k + delta),
+//   S_k = clamp(y* St_k, delta, 1),  C_k = St_k^2 / (S_k + St_k)
+//   dV_I^2  = (St_i - St_j)/(St_i + St_j) (C_i - A_i - q + A_j)
+//   dV_II^2 = 2 (S_i - delta) + C_i - B_i + q - B_j,   q = St_j^2 / (S_i + St_j)
+// ---------------------------------------------------------------------------
+// Constants of one cell.
+struct CellRate {
+    double delta, vt_scale, kbt, vf, rg_vth, Om;
+    bool turb;
+};
+
+__device__ inline CellRate cell_rate(const CellArrays &cells, const double *v_frag, long c) {
+    CellRate r;
+    const double c_s = cells.c_s[c], alpha = cells.alpha[c];
+    r.turb = alpha > 0.0;
+    r.delta = r.turb ? 1.0 / sqrt(alpha * c_s * cells.H[c] / cells.nu_mol[c]) : 0.0;
+    r.vt_scale = alpha * c_s * c_s;
+    r.kbt = 8.0 * kBoltzmann * cells.T[c] / M_PI;
+    r.vf = v_frag[c];
+    r.rg_vth = cells.rho_g[c] * (sqrt(8.0 / M_PI) * c_s);      // rho_g v_th
+    r.Om = cells.Omega[c];
+    return r;
+}
+
+// One grain of one cell: St, A, B, C above, velocity, 1/m, radius; and, for
+// the heavier grain of a pair, S, u = C - A and w = 2 (S - delta) + C - B.
+struct Grain {
+    double st, a, bt, ct, vx, vy, vz, im, s;
+    double S, u, w;
+};
+
+__device__ inline double stir_s(const CellRate &r, double st) {
+    return fmin(fmax(kYStar * st, r.delta), 1.0);
+}
+
+// A, B, C of a grain of Stokes number st
+__device__ inline void grain_abc(const CellRate &r, double st, Grain &g) {
+    const double a = st * st;
+    g.st = st;
+    g.a = a / (1.0 + st);
+    g.bt = r.turb ? a / (st + r.delta) : 0.0;
+    g.ct = a / (stir_s(r, st) + st);
+}
+
+// St, A, B, C of a grain of radius s (material density rho_m)
+__device__ inline void grain_terms(const CellRate &r, double rho_m, double s, Grain &g) {
+    grain_abc(r, rho_m * s / r.rg_vth * r.Om, g);
+}
+
+// the heavier grain's S, u, w (S given)
+__device__ inline void heavier_terms(const CellRate &r, Grain &g, double S) {
+    g.S = S;
+    g.u = g.ct - g.a;
+    g.w = 2.0 * (S - r.delta) + g.ct - g.bt;
+}
+
+// Kc, Kf of the pair (i, j), i >= j (i the grain with the larger St; its
+// heavier_terms set)
+__device__ inline void pair_rates(const CellRate &r, const Grain &gi, const Grain &gj, bool diag,
+                                  double &kc, double &kf) {
+    double vturb2 = 0.0;
+    if (r.turb) {
+        const double si = gi.st, sj = gj.st;
+        const double q = sj * sj / (gi.S + sj);
+        const double dV1 = (si - sj) / (si + sj) * (gi.u - q + gj.a);
+        const double dV2 = gi.w + q - gj.bt;
+        vturb2 = r.vt_scale * (dV1 + dV2);
+    }
+    const double dx = gi.vx - gj.vx, dy = gi.vy - gj.vy, dz = gi.vz - gj.vz;
+    const double dv = sqrt(r.kbt * (gi.im + gj.im) + vturb2 + (dx * dx + dy * dy + dz * dz));
+    const double ss = gi.s + gj.s;
+    const double K = M_PI * ss * ss * dv * (diag ? 0.5 : 1.0);
+    double pf, pc;
+    if (dv == 0.0) {
+        pf = 0.0;
+        pc = 1.0;
+    } else {
+        const double qv = r.vf / dv;
+        const double y = 1.5 * qv * qv;
+        pf = (1.0 + y) * exp(-y);
+        pc = y < kSeriesY
+                 ? y * y * (1.0 / 2.0 + y * (-1.0 / 3.0 + y * (1.0 / 8.0 + y * (-1.0 / 30.0 +
+                   y * (1.0 / 144.0 + y * (-1.0 / 840.0 + y * (1.0 / 5760.0)))))))
+                 : 1.0 - pf;
+    }
+    kc = K * pc;
+    kf = K * pf;
+}
+
+// Pair rates of one block of 16 cells (cells cell0 .. cell0 + 15) in the
+// 16-cell-blocked layout (rate of cell c, pair p at ((c / 16) P + p) 16 +
+// c % 16; cells past C get zeros), double or rounded to float, by NT threads
+// of a workgroup: thread t works on cell t % 16 and pairs t / 16 + (NT / 16) k,
+// so that the 16 cells of a pair leave as one run (64 bytes in FP32, a
+// 128-byte line in FP64).  Per-grain values in `lds` as [value][bin][cell]
+// (the lanes of a pair read 16 consecutive doubles).  TAB = 7 tabulates St, A,
+// B, C and the velocity; for grids whose 16 cells' values would not fit LDS
+// otherwise, TAB = 6 leaves out C and TAB = 1 keeps St only (the velocity then
+// read from v_dust); what is left out follows from St where it is used, by
+// the same arithmetic.
+template <int TAB>
+inline size_t rates_blk_lds_bytes(int N) { return (size_t)(16 * TAB + 2) * N * sizeof(double); }
+
+template <int TAB, int NT, typename OT>
+__device__ void rates_block(const Tables &T, const CellArrays &cells,
+                            const double *__restrict__ v_dust, const double *__restrict__ v_frag,
+                            OT *__restrict__ Kc, OT *__restrict__ Kf, long C, long cell0,
+                            double *lds) {
+    static_assert(TAB == 7 || TAB == 6 || TAB == 1, "tabulated values per grain");
+    static_assert(NT % 64 == 0, "whole waves");
+    constexpr int VX = TAB - 3;                       // first velocity row (TAB >= 6)
+    constexpr int SLOTS = NT / 16;
+    const int N = T.N, P = T.P;
+    double *tb = lds, *sv = lds + 16 * TAB * N, *imv = sv + N;
+    auto tab = [&](int v, int k, int cl) -> double & { return tb[(v * N + k) * 16 + cl]; };
+    for (int t = threadIdx.x; t < 16 * N; t += NT) {
+        const int cl = t & 15, k = t >> 4;
+        const long c = cell0 + cl;
+        Grain g{};
+        if (c < C) {
+            grain_terms(cell_rate(cells, v_frag, c), T.rho_m, T.s[k], g);
+            if (TAB >= 6) {
+                const double *v = v_dust + (c * N + k) * 3;
+                g.vx = v[0];
+                g.vy = v[1];
+                g.vz = v[2];
+            }
+        }
+        tab(0, k, cl) = g.st;
+        if (TAB >= 6) {
+            tab(1, k, cl) = g.a;
+            tab(2, k, cl) = g.bt;
+            if (TAB == 7) tab(3, k, cl) = g.ct;
+            tab(VX, k, cl) = g.vx;
+            tab(VX + 1, k, cl) = g.vy;
+            tab(VX + 2, k, cl) = g.vz;
+        }
+    }
+    for (int k = threadIdx.x; k < N; k += NT) {
+        sv[k] = T.s[k];
+        imv[k] = 1.0 / T.m[k];
+    }
+    __syncthreads();
+    const int cl = threadIdx.x & 15, slot = threadIdx.x >> 4;
+    const long c = cell0 + cl;
+    const bool live = c < C;
+    const CellRate r = cell_rate(cells, v_frag, live ? c : C - 1);
+    const double *vc = v_dust + (live ? c : C - 1) * N * 3;
+    auto grain = [&](int k) {
+        Grain g;
+        if (TAB >= 6) {
+            g.st = tab(0, k, cl);
+            g.a = tab(1, k, cl);
+            g.bt = tab(2, k, cl);
+            if (TAB == 7) g.ct = tab(3, k, cl);
+            g.vx = tab(VX, k, cl);
+            g.vy = tab(VX + 1, k, cl);
+            g.vz = tab(VX + 2, k, cl);
+        } else {
+            grain_abc(r, tab(0, k, cl), g);
+            g.vx = vc[3 * k];
+            g.vy = vc[3 * k + 1];
+            g.vz = vc[3 * k + 2];
+        }
+        g.im = imv[k];
+        g.s = sv[k];
+        return g;
+    };
+    OT *kc = Kc + cell0 * P + cl, *kf = Kf + cell0 * P + cl;
+    uint32_t ijn = slot < P ? T.pij[slot] : 0u;
+    for (int p = slot; p < P; p += SLOTS) {
+        const uint32_t ij = ijn;
+        if (p + SLOTS < P) ijn = T.pij[p + SLOTS];
+        OT oc = (OT)0, of = (OT)0;
+        if (live) {
+            const int i = pair_i(ij), j = pair_j(ij);
+            Grain gi = grain(i);
+            const double S = stir_s(r, gi.st);
+            if (TAB == 6) gi.ct = gi.st * gi.st / (S + gi.st);
+            heavier_terms(r, gi, S);
+            double c64, f64;
+            pair_rates(r, gi, grain(j), i == j, c64, f64);
+            oc = (OT)c64;
+            of = (OT)f64;
+        }
+        kc[(long)p * 16] = oc;
+        kf[(long)p * 16] = of;
+    }
+}
+
+// the table size rates_block takes at N bins (7, 6, or 1 values per grain)
+inline int rates_blk_tab(int N, size_t lds_cap) {
+    if (rates_blk_lds_bytes<7>(N) <= lds_cap) return 7;
+    if (rates_blk_lds_bytes<6>(N) <= lds_cap) return 6;
+    return 1;
+}
+
+}  // namespace coag
