@@ -358,18 +358,19 @@ __global__ __launch_bounds__(BLOCK) void k_step(Tables T, StepArgs a) {
 // Reverse sweep over the frozen steps of one cell.  The forward replay keeps
 // every step's state and its two inner stage states (y2, y3) in the workspace,
 // so the sweep evaluates only the three vector-Jacobian products per step.
-// dJ/dKc, dJ/dKf are summed in LDS over the whole sweep when they fit
-// (gk_lds), else in the global workspace.
+// dJ/dKc, dJ/dKf are summed over the whole sweep in the global workspace,
+// each pair owned by one thread: with only the sweep's 14N doubles in LDS,
+// several workgroups share a CU (summing them in LDS instead, 2P more doubles,
+// left one workgroup per CU and ran the backward pass 25 % slower).
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_adjoint(Tables T, AdjArgs a, int gk_lds) {
+__global__ __launch_bounds__(BLOCK) void k_adjoint(Tables T, AdjArgs a) {
     extern __shared__ double lds[];
     const long c = blockIdx.x;
     const int N = T.N, P = T.P;
     double *lam = lds, *mu = lds + N, *k1 = lds + 2 * N, *k2 = lds + 3 * N, *k3 = lds + 4 * N,
            *v3 = lds + 6 * N, *v2 = lds + 7 * N, *v1 = lds + 8 * N, *scratch = lds + 9 * N;
     const double *Kc = a.Kc + c * P, *Kf = a.Kf + c * P;
-    double *gKc = gk_lds ? lds + 14 * N : a.gKc + c * P;
-    double *gKf = gk_lds ? lds + 14 * N + P : a.gKf + c * P;
+    double *gKc = a.gKc + c * P, *gKf = a.gKf + c * P;
     double *Ys = a.Ys + c * (long)(a.log_stride + 1) * N;
     double *Zs = a.Zs + c * (long)a.log_stride * 2 * N;      // y2, y3 of every step
     const double *hl = a.h_log + c * (long)a.log_stride;
@@ -422,12 +423,6 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Tables T, AdjArgs a, int gk_l
         __syncthreads();
     }
     for (int k = threadIdx.x; k < N; k += BLOCK) a.g_in[c * N + k] = ok ? lam[k] : NAN;
-    if (gk_lds) {
-        for (int p = threadIdx.x; p < P; p += BLOCK) {
-            a.gKc[c * P + p] = gKc[p];
-            a.gKf[c * P + p] = gKf[p];
-        }
-    }
 }
 
 // dJ/dalpha and dJ/dv_frag per cell from dJ/dKc, dJ/dKf and the hand-derived
@@ -605,12 +600,9 @@ hipError_t launch_adjoint(const Tables &T, long C, const AdjArgs &a, const CellA
                           const double *v_dust, const double *v_frag, double *g_alpha,
                           double *g_vfrag, hipStream_t st) {
     if (C == 0) return hipSuccess;
-    // dJ/dK in LDS when 2P more doubles fit beside the 14N of the sweep
-    const size_t with_gk = lds_bytes(14 * T.N + 2 * T.P);
-    const int gk_lds = with_gk <= 160 * 1024;
-    const size_t bytes = gk_lds ? with_gk : lds_bytes(14 * T.N);
+    const size_t bytes = lds_bytes(14 * T.N);
     if (hipError_t e = allow_lds(k_adjoint<kBlock>, bytes)) return e;
-    hipLaunchKernelGGL(k_adjoint<kBlock>, dim3((unsigned)C), dim3(kBlock), bytes, st, T, a, gk_lds);
+    hipLaunchKernelGGL(k_adjoint<kBlock>, dim3((unsigned)C), dim3(kBlock), bytes, st, T, a);
     hipLaunchKernelGGL(k_rate_grad<kBlock>, dim3((unsigned)C), dim3(kBlock),
                        lds_bytes(4 * T.N + 64), st, T, cells, v_dust, v_frag, a.gKc, a.gKf,
                        g_alpha, g_vfrag);
