@@ -611,13 +611,16 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             B0.u = bb[u & 1][0];
             B1.u = bb[u & 1][1];
             B2.u = bb[u & 1][2];
-            f32x4 &acc = acc32[u & 1];                 // one chunk per FP32 accumulation
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B0.v, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B1.v, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B0.v, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B2.v, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B1.v, acc, 0, 0, 0);
+            // one chunk per FP32 accumulation, the limb products smallest
+            // first (order 2, 1, 0): each MFMA rounds its sum to FP32 once, so
+            // the corrections are summed before they meet the a0 b0 term
+            f32x4 &acc = acc32[u & 1];
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a2, B0.v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B1.v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B2.v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a1, B0.v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B1.v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.a0, B0.v, acc, 0, 0, 0);
             if (prev >= 0) flush_tile(prev, (u + 1) & 1);
             prev = i;
             next_k(rk[u]);
