@@ -165,3 +165,44 @@ def test_split_rejections_and_host_errors(O):
     assert e.value.code == L.COAG_ENOTSUP
     torch.cuda.synchronize()
     assert torch.equal(rho, before)
+
+
+@pytest.mark.parametrize("name", ["disc256x128_n150", "disc512x256_n200"])
+def test_split_error_on_spread_sample(name):
+    """The bench's measurement as a test: 512 cells spread over the full disc
+    (cells evolve independently, so the sample alone takes the same path),
+    three FP64 calls of dt from the MRN start, then one FP64 call over 20 dt
+    that the split step (blocked FP32 rates) replays.  Bar: 1e-6 relative in
+    resolved bins (>= 1e-12 of the cell's mass), 1e-18 of the cell's mass in
+    the rest, total mass to 1e-12."""
+    from paper_2402_18471_amd import _lib as L
+    from paper_2402_18471_amd import disc
+    from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
+    cfg = disc.CONFIGS[name]
+    m, me, s = coag_mass_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
+    d = disc.make_disc(cfg, s)
+    idx = np.arange(0, cfg.n_cells, cfg.n_cells // 512)
+    sub = disc.subset_cells(d, idx)
+    ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
+    cells = {k: _t(v) for k, v in sub["cells"].items()}
+    vd, vf = _t(sub["v_dust"]), _t(sub["v_frag"])
+    K64 = ctx.coag_rates(cells, vd, vf)
+    K32 = ctx.coag_rates_blocked(cells, vd, vf)
+    rho = _t(sub["rho"])
+    h = torch.zeros(len(idx), dtype=torch.float64, device=DEV)
+    for _ in range(3):
+        r = ctx.coag_step(rho, *K64, d["dt"], h=h, max_sub=512)
+        assert np.all(_np(r["status"]) == 0)
+    rho0 = rho.clone()
+    a = ctx.coag_step(rho0.clone(), *K64, 20 * d["dt"], max_sub=512)
+    b = ctx.coag_step(rho0.clone(), *K32, 20 * d["dt"], mode=L.REPLAY, prec=1,
+                      nsub=a["nsub"].clone(), h_log=a["h_log"])
+    torch.cuda.synchronize()
+    assert np.all(_np(a["status"]) == 0) and np.all(_np(b["status"]) == 0)
+    x, ref = _np(b["rho"]), _np(a["rho"])
+    M = ref.sum(1, keepdims=True)
+    res = ref >= 1e-12 * M
+    err = np.abs(x - ref)
+    assert np.max(err[res] / ref[res]) <= 1e-6, np.max(err[res] / ref[res])
+    assert np.max((err / M)[~res], initial=0.0) <= 1e-18
+    assert np.max(np.abs(x.sum(1) / _np(rho0).sum(1) - 1)) <= 1e-12
