@@ -75,6 +75,29 @@ __device__ inline void heavier_terms(const CellRate &r, Grain &g, double S) {
     g.w = 2.0 * (S - r.delta) + g.ct - g.bt;
 }
 
+// a / b and 1 / sqrt(x) for the per-pair arithmetic, whose operands are
+// normal, finite and positive: the hardware estimates refined by Newton's
+// iteration (reciprocal: r <- r + r (1 - b r), twice, then the quotient
+// corrected once, q <- q + r (a - b q); reciprocal square root:
+// r <- r (3/2 - x r^2 / 2), twice).  Within an ulp or two of the rounded
+// results, in fewer instructions than the IEEE sequences, which also scale
+// for denormal and overflowing operands.
+__device__ __forceinline__ double div_nr(double a, double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(fma(-b, r, 1.0), r, r);
+    r = fma(fma(-b, r, 1.0), r, r);
+    const double q = a * r;
+    return fma(fma(-b, q, a), r, q);
+}
+
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    r = r * fma(-hx * r, r, 1.5);
+    r = r * fma(-hx * r, r, 1.5);
+    return r;
+}
+
 // Kc, Kf of the pair (i, j), i >= j (i the grain with the larger St; its
 // heavier_terms set)
 __device__ inline void pair_rates(const CellRate &r, const Grain &gi, const Grain &gj, bool diag,
@@ -82,21 +105,24 @@ __device__ inline void pair_rates(const CellRate &r, const Grain &gi, const Grai
     double vturb2 = 0.0;
     if (r.turb) {
         const double si = gi.st, sj = gj.st;
-        const double q = sj * sj / (gi.S + sj);
-        const double dV1 = (si - sj) / (si + sj) * (gi.u - q + gj.a);
+        const double q = div_nr(sj * sj, gi.S + sj);
+        const double dV1 = div_nr(si - sj, si + sj) * (gi.u - q + gj.a);
         const double dV2 = gi.w + q - gj.bt;
         vturb2 = r.vt_scale * (dV1 + dV2);
     }
     const double dx = gi.vx - gj.vx, dy = gi.vy - gj.vy, dz = gi.vz - gj.vz;
-    const double dv = sqrt(r.kbt * (gi.im + gj.im) + vturb2 + (dx * dx + dy * dy + dz * dz));
+    // dv = sqrt(dv2) = dv2 / sqrt(dv2), and y = 1.5 (v_frag / dv)^2 = 1.5 v_frag^2 / dv2
+    const double dv2 = r.kbt * (gi.im + gj.im) + vturb2 + (dx * dx + dy * dy + dz * dz);
+    const double rs = dv2 > 0.0 ? rsqrt_nr(dv2) : 0.0;
+    const double dv = dv2 > 0.0 ? dv2 * rs : sqrt(dv2);
     const double ss = gi.s + gj.s;
     const double K = M_PI * ss * ss * dv * (diag ? 0.5 : 1.0);
     double pf, pc;
-    if (dv == 0.0) {
+    if (!(dv2 > 0.0)) {
         pf = 0.0;
         pc = 1.0;
     } else {
-        const double qv = r.vf / dv;
+        const double qv = r.vf * rs;
         const double y = 1.5 * qv * qv;
         pf = (1.0 + y) * exp(-y);
         pc = y < kSeriesY
