@@ -393,8 +393,9 @@ def main():
         evolve(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(the cell-parallel path would shard by radial rings, see DESIGN.md)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
+                          "(cells are independent: the path would shard by radial rings dealt "
+                          "cyclically over the GPUs)"}))
         sys.exit(2)
     import torch
     from paper_2402_18471_amd import disc

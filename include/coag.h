@@ -9,6 +9,8 @@
  * other cell.  Four calls make up the path:
  *
  *   coag_rates          pair rates  Kc = w K p_coag,  Kf = w K p_frag
+ *                       (coag_rates_blocked: the same in the 16-cell-blocked
+ *                       layout the batched step streams, FP64 or FP32)
  *   coag_rhs            drho/dt  (eq. `smol`)
  *   coag_step           sub-cycled Bogacki-Shampine 3(2) over dt
  *   coag_step_backward  adjoint of a frozen step sequence
@@ -201,8 +203,9 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
      status  [C] int32     DEVICE out, COAG_CELL_*
    Arithmetic (tol->prec):
      COAG_PREC_FP64: everything in FP64.  Where the grid allows it (N >= 16,
-       the products of each row of pairs within 16 consecutive bins, N <= 400)
-       16 cells advance together and the gain sum runs on FP64 matrix cores;
+       the products of each row of pairs within 16 consecutive bins, and
+       N <= 343 so that the state of 16 cells fits LDS) 16 cells advance
+       together and the gain sum runs on FP64 matrix cores;
        otherwise one workgroup per cell.  The environment variable
        COAG_STEP_KERNEL=cell, read by coag_create, forces the latter.
      COAG_PREC_SPLIT_BF16: the gain sum sum_p n_i n_j K_p D_pk runs as BF16

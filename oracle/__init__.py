@@ -9,7 +9,9 @@ Every function follows Robinson, Booth & Owen (cuDisc), Sec. 5 (dust growth and
 fragmentation): eqs. ``smol``, ``ngain``, ``kernel``, ``vbrown``, ``OCVrel``,
 ``p_frag``, ``Cijk``, ``Rijk``, ``Nijk``, ``fragrem`` and the Bogacki-Shampine
 3(2) integrator with the tolerances of that section; the sub-cycling rule is
-Sec. 6.  Readings of silent or ambiguous points are listed in the design doc.
+Sec. 6.  Where the paper is silent or ambiguous the reading taken is stated at
+the function that takes it (grid edges, the two-bin split, the loss indices,
+the step-size controller).
 
 Packed pair index: p(i, j) = i (i + 1) / 2 + j for j <= i.
 """

@@ -290,7 +290,7 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void 
         !batch_available(ctx->T, ctx->B))
         return fail(ctx, COAG_ENOTSUP,
                     "coag_step: the split-BF16 step and blocked rates need N >= 16 bins whose "
-                    "products of each row fit a 16-bin window, and N <= 400");
+                    "products of each row fit a 16-bin window, and N <= 343");
     if (layout == COAG_RATES_BLK64 && !ctx->batch_fp64)
         return fail(ctx, COAG_ENOTSUP,
                     "coag_step: blocked FP64 rates need the batched step "

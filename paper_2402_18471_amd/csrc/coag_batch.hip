@@ -230,13 +230,14 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
     // workspace of cell c: k1, k2, k3, k4, yn, each [N]
     auto wsp = [&](int c, int v) { return ws + ((cell0 + c) * 5 + v) * (long)N; };
 
-    // ---- FP64 form: the batch's rates, reordered once per call: pair-major,
-    // then kind (Kc, Kf), then the 16 cells, so that every right-hand side
-    // streams whole cache lines (rows of [C][P] are P elements apart).  Staged
-    // through LDS tiles of TP pairs (rows padded by one element against bank
-    // conflicts).  The split form reads FP32 rates in the 16-cell-blocked
-    // layout that coag_rates_f32 writes (whole 64-byte runs per pair), and FP64
-    // rates as [C][P].
+    // ---- FP64 form fed [C][P] rates: the batch's rates, reordered once per
+    // call: pair-major, then kind (Kc, Kf), then the 16 cells, so that every
+    // right-hand side streams whole cache lines (rows of [C][P] are P elements
+    // apart).  Staged through LDS tiles of TP pairs (rows padded by one element
+    // against bank conflicts).  Fed the 16-cell-blocked rates of
+    // coag_rates_blocked (BLK), both forms read them in place: a 128-byte line
+    // (FP64) or 64-byte run (FP32) per pair; the split form reads FP64 [C][P]
+    // rates directly.
     RT *const kb = wk + (long)blockIdx.x * P * 2 * kBC;
     if (PREC == 0 && !BLK) {
         RT *tile = (RT *)lds;
