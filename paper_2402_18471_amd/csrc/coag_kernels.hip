@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kRatesBlock) void k_rates(Tables T, CellArrays cell
 }
 
 // Pair rates in the 16-cell-blocked layout, 16 cells per workgroup of 1024
-// threads (rates_block).
+// threads (rates_block); blockIdx.y takes slice y of gridDim.y of the pairs.
 template <int TAB, typename OT>
 __global__ __launch_bounds__(1024) void k_rates_blk(Tables T, CellArrays cells,
                                                     const double *__restrict__ v_dust,
@@ -199,7 +199,11 @@ __global__ __launch_bounds__(1024) void k_rates_blk(Tables T, CellArrays cells,
                                                     OT *__restrict__ Kc, OT *__restrict__ Kf,
                                                     long C) {
     extern __shared__ double lds[];
-    rates_block<TAB, 1024>(T, cells, v_dust, v_frag, Kc, Kf, C, (long)blockIdx.x * 16, lds);
+    const int P = T.P;
+    const int p0 = (int)((long)P * blockIdx.y / gridDim.y);
+    const int p1 = (int)((long)P * (blockIdx.y + 1) / gridDim.y);
+    rates_block<TAB, 1024>(T, cells, v_dust, v_frag, Kc, Kf, C, (long)blockIdx.x * 16, p0, p1,
+                           lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -554,13 +558,16 @@ static hipError_t launch_rates_blk(const Tables &T, long C, const CellArrays &ce
                                    const double *v_dust, const double *v_frag, OT *Kc, OT *Kf,
                                    hipStream_t st) {
     const unsigned blocks = (unsigned)((C + 15) / 16);
+    // few blocks (small grids of cells): share each block's pairs among
+    // several workgroups, so that at least ~512 run
+    const unsigned slices = blocks >= 512 ? 1u : min(8u, (512u + blocks - 1) / blocks);
     const int tab = rates_blk_tab(T.N, 160 * 1024);
 #define RATES_BLK(TAB)                                                                            \
     {                                                                                             \
         const size_t bytes = rates_blk_lds_bytes<TAB>(T.N);                                       \
         if (hipError_t e = allow_lds(k_rates_blk<TAB, OT>, bytes)) return e;                      \
-        hipLaunchKernelGGL((k_rates_blk<TAB, OT>), dim3(blocks), dim3(1024), bytes, st, T, cells, \
-                           v_dust, v_frag, Kc, Kf, C);                                            \
+        hipLaunchKernelGGL((k_rates_blk<TAB, OT>), dim3(blocks, slices), dim3(1024), bytes, st, T,  \
+                           cells, v_dust, v_frag, Kc, Kf, C);                                     \
     }
     if (tab == 7) RATES_BLK(7)
     else if (tab == 6) RATES_BLK(6)

@@ -144,7 +144,8 @@ __device__ inline void pair_rates(const CellRate &r, const Grain &gi, const Grai
 // B, C and the velocity; for grids whose 16 cells' values would not fit LDS
 // otherwise, TAB = 6 leaves out C and TAB = 1 keeps St only (the velocity then
 // read from v_dust); what is left out follows from St where it is used, by
-// the same arithmetic.
+// the same arithmetic.  Only pairs in [p0, p1) are written (a block's pairs
+// may be shared among several workgroups).
 template <int TAB>
 inline size_t rates_blk_lds_bytes(int N) { return (size_t)(16 * TAB + 2) * N * sizeof(double); }
 
@@ -152,7 +153,7 @@ template <int TAB, int NT, typename OT>
 __device__ void rates_block(const Tables &T, const CellArrays &cells,
                             const double *__restrict__ v_dust, const double *__restrict__ v_frag,
                             OT *__restrict__ Kc, OT *__restrict__ Kf, long C, long cell0,
-                            double *lds) {
+                            int p0, int p1, double *lds) {
     static_assert(TAB == 7 || TAB == 6 || TAB == 1, "tabulated values per grain");
     static_assert(NT % 64 == 0, "whole waves");
     constexpr int VX = TAB - 3;                       // first velocity row (TAB >= 6)
@@ -214,10 +215,10 @@ __device__ void rates_block(const Tables &T, const CellArrays &cells,
         return g;
     };
     OT *kc = Kc + cell0 * P + cl, *kf = Kf + cell0 * P + cl;
-    uint32_t ijn = slot < P ? T.pij[slot] : 0u;
-    for (int p = slot; p < P; p += SLOTS) {
+    uint32_t ijn = p0 + slot < p1 ? T.pij[p0 + slot] : 0u;
+    for (int p = p0 + slot; p < p1; p += SLOTS) {
         const uint32_t ij = ijn;
-        if (p + SLOTS < P) ijn = T.pij[p + SLOTS];
+        if (p + SLOTS < p1) ijn = T.pij[p + SLOTS];
         OT oc = (OT)0, of = (OT)0;
         if (live) {
             const int i = pair_i(ij), j = pair_j(ij);
