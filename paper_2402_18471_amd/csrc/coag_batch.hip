@@ -205,13 +205,27 @@ __device__ __forceinline__ double wave_min_d(double v) {
     return v;
 }
 
+// The batch a workgroup takes.  Workgroups are dealt to the eight XCDs in
+// turn (workgroup w to XCD w mod 8), and each XCD runs its share from its own
+// queue, so with the plain mapping XCD x would take every batch b = x mod 8:
+// on a disc stored radius by radius with eight batches per radius, always the
+// same height above the midplane, and the XCD with the stiffest layer would
+// finish last.  Workgroup 8k + x takes batch 8k + (x + k) mod 8 instead (the
+// last, incomplete group of eight keeps the plain mapping): each XCD sees
+// every layer, and batches still start in about index order.
+__device__ __forceinline__ long batch_of(long w, long nb) {
+    const long k = w >> 3;
+    return 8 * k + 8 > nb ? w : 8 * k + ((w + k) & 7);
+}
+
 template <int PREC, typename RT, bool BLK>
 __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B, StepArgs a,
                                                         long C, double *ws, RT *wk) {
     extern __shared__ double lds[];
     const int N = T.N;
     const long P = T.P;
-    const long cell0 = (long)blockIdx.x * kBC;
+    const long bt = batch_of(blockIdx.x, gridDim.x);
+    const long cell0 = bt * kBC;
     double *nv = lds, *net = lds + kBC * N, *phi = lds + 2 * kBC * N, *mk = lds + 3 * kBC * N;
     int *fcol = (int *)(mk + N), *frow = fcol + N, *wbl = frow + N;
     float *nf = (float *)(fcol + 4 * N);          // split form: [16][N] n_k / max_k n_k
@@ -238,7 +252,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
     // coag_rates_blocked (BLK), both forms read them in place: a 128-byte line
     // (FP64) or 64-byte run (FP32) per pair; the split form reads FP64 [C][P]
     // rates directly.
-    RT *const kb = wk + (long)blockIdx.x * P * 2 * kBC;
+    RT *const kb = wk + bt * P * 2 * kBC;
     if (PREC == 0 && !BLK) {
         RT *tile = (RT *)lds;
         const int cap = (int)((3 * kBC * N * sizeof(double)) / (2 * kBC * sizeof(RT))) - 1;

@@ -154,7 +154,11 @@ KERNELS = ["batch", "cell"]
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("case", [("disc64x32_n100", 8, 4, None),
                                   ("disc256x128_n150", 4, 2, None),
-                                  ("disc64x32_n100", 5, 7, None)])
+                                  ("disc64x32_n100", 5, 7, None),
+                                  # 20 batches of 16 cells: two whole groups of eight
+                                  # workgroups (the second dealt to the XCDs rotated)
+                                  # and a group of four
+                                  ("disc64x32_n100", 20, 16, None)])
 def test_step_fixed_parity(O, case, kernel):
     cfg, g, d, ctx, cells = _case(O, *case, kernel=kernel)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
