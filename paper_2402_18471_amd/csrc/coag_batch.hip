@@ -531,22 +531,27 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             acc32[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         };
         // this lane's lighter grains in column block q (both kinds of four
-        // pairs), and their running sums
+        // pairs), and their running sums: all rates of grain j, and its
+        // fragmenting rates against the targets it craters.  A cratering
+        // projectile j makes fragments of mass (1 + chi) m_j (itself and the
+        // mass it excavates, eq. `fragrem`), all at the top bin of j, so the
+        // factor is applied once per block.
         constexpr int NJ = 4;
         auto jof = [&](int q, int u) { return 16 * q + 4 * g + u; };
-        double colsum[NJ], fragsum[NJ];
+        double colsum[NJ], cratsum[NJ];
 #pragma unroll
-        for (int u = 0; u < NJ; ++u) colsum[u] = fragsum[u] = 0.0;
+        for (int u = 0; u < NJ; ++u) colsum[u] = cratsum[u] = 0.0;
         auto flush_cols = [&](int q) {
 #pragma unroll
             for (int u = 0; u < NJ; ++u) {
                 const int j = jof(q, u);
                 if (j < N) {
-                    atomicAdd(&netc[j], -mk[j] * colsum[u]);
-                    atomicAdd(&phic[fcol[j]], fragsum[u]);
+                    const double mj = mk[j];
+                    atomicAdd(&netc[j], -mj * colsum[u]);
+                    atomicAdd(&phic[fcol[j]], (1.0 + chi) * mj * cratsum[u]);
                 }
                 colsum[u] = 0.0;
-                fragsum[u] = 0.0;
+                cratsum[u] = 0.0;
             }
         };
         int colq = cq, prev = -1;
@@ -593,12 +598,14 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             // x = n_j K / max n (FP32, the MFMA operand); the FP64 rate of
             // the pair for the column terms is (n_i max n) x.  Column terms:
             // the rate sums, and fragments (crater: summed for the block;
-            // destroyed target: summed for the chunk, all at the top bin of
-            // m_i)
+            // destroyed target, mass m_i + m_j: summed for the chunk, all at
+            // the top bin of m_i).  Grain i craters every grain of the block
+            // when it craters the heaviest (chi m_j < m_i), the case of all
+            // but the chunks near the diagonal.
             const double c64 = nrow[i] * nmax, mi = mk[i];
             float x[8];
             double dest = 0.0;
-            auto pairs = [&](bool full) {
+            auto pairs = [&](bool full, bool crat) {
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const int j = 16 * q + 4 * g + s;
@@ -607,17 +614,25 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                     const float nj = nfr[jc];
                     x[s] = ok ? nj * (float)rk[u][s] : 0.0f;
                     x[4 + s] = ok ? nj * (float)rk[u][4 + s] : 0.0f;
-                    const double rc = c64 * (double)x[s], rf = c64 * (double)x[4 + s];
-                    colsum[s] += rc + rf;
-                    bool crater;
-                    const double fr = frag_mass(mi, mk[jc], chi, crater) * rf;
-                    fragsum[s] += crater ? fr : 0.0;
-                    dest += crater ? 0.0 : fr;
+                    const double xf = (double)x[4 + s];
+                    colsum[s] = fma(c64, (double)x[s] + xf, colsum[s]);
+                    if (crat) {
+                        cratsum[s] = fma(c64, xf, cratsum[s]);
+                    } else {
+                        const double mj = mk[jc], rf = c64 * xf;
+                        const bool crater = chi * mj < mi;
+                        cratsum[s] += crater ? rf : 0.0;
+                        dest += crater ? 0.0 : (mi + mj) * rf;
+                    }
                 }
             };
-            if (16 * q + 15 <= i) pairs(true);
-            else pairs(false);
-            atomicAdd(&phic[frow[i]], dest);
+            if (16 * q + 15 <= i && chi * mk[16 * q + 15] < mi) {
+                pairs(true, true);
+            } else {
+                if (16 * q + 15 <= i) pairs(true, false);
+                else pairs(false, false);
+                atomicAdd(&phic[frow[i]], dest);
+            }
             const Limbs8 L = split3x8(x);
             union {
                 uint4 u;
