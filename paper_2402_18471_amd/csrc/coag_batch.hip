@@ -554,7 +554,20 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                 cratsum[u] = 0.0;
             }
         };
+        // n_j / max n of the lane's four lighter grains (zero past the grid)
+        // and chi m_j of the block's heaviest: constant over a column block
+        float njv[NJ];
+        double mq = 0.0;
+        auto load_cols = [&](int q) {
+#pragma unroll
+            for (int u = 0; u < NJ; ++u) {
+                const int j = jof(q, u);
+                njv[u] = j < N ? nfr[j] : 0.0f;
+            }
+            mq = chi * mk[16 * q + 15 < N ? 16 * q + 15 : N - 1];
+        };
         int colq = cq, prev = -1;
+        load_cols(colq);
         // lane (cell, g): pairs 16q + 4g + s, s = 0..3, Kc in k[s], Kf in
         // k[4 + s] (the K rows of the MFMA operands)
         // FP32 rates: pair p of the batch's cell cl at p * 16 + cl (padding
@@ -594,6 +607,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             if (q != colq) {
                 flush_cols(colq);
                 colq = q;
+                load_cols(q);
             }
             // x = n_j K / max n (FP32, the MFMA operand); the FP64 rate of
             // the pair for the column terms is (n_i max n) x.  Column terms:
@@ -611,9 +625,8 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                     const int j = 16 * q + 4 * g + s;
                     const bool ok = full || j <= i;
                     const int jc = ok ? j : i;
-                    const float nj = nfr[jc];
-                    x[s] = ok ? nj * (float)rk[u][s] : 0.0f;
-                    x[4 + s] = ok ? nj * (float)rk[u][4 + s] : 0.0f;
+                    x[s] = ok ? njv[s] * (float)rk[u][s] : 0.0f;
+                    x[4 + s] = ok ? njv[s] * (float)rk[u][4 + s] : 0.0f;
                     const double xf = (double)x[4 + s];
                     colsum[s] = fma(c64, (double)x[s] + xf, colsum[s]);
                     if (crat) {
@@ -626,7 +639,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                     }
                 }
             };
-            if (16 * q + 15 <= i && chi * mk[16 * q + 15] < mi) {
+            if (16 * q + 15 <= i && mq < mi) {
                 pairs(true, true);
             } else {
                 if (16 * q + 15 <= i) pairs(true, false);
