@@ -111,10 +111,12 @@ __device__ inline void pair_rates(const CellRate &r, const Grain &gi, const Grai
         vturb2 = r.vt_scale * (dV1 + dV2);
     }
     const double dx = gi.vx - gj.vx, dy = gi.vy - gj.vy, dz = gi.vz - gj.vz;
-    // dv = sqrt(dv2) = dv2 / sqrt(dv2), and y = 1.5 (v_frag / dv)^2 = 1.5 v_frag^2 / dv2
+    // dv = sqrt(dv2) = dv2 / sqrt(dv2), and y = 1.5 (v_frag / dv)^2 = 1.5 v_frag^2 / dv2;
+    // where dv2 > 0 fails (dv2 = 0, or NaN), dv = dv2 * 0 is 0 or NaN, as its
+    // square root would be, without evaluating one
     const double dv2 = r.kbt * (gi.im + gj.im) + vturb2 + (dx * dx + dy * dy + dz * dz);
     const double rs = dv2 > 0.0 ? rsqrt_nr(dv2) : 0.0;
-    const double dv = dv2 > 0.0 ? dv2 * rs : sqrt(dv2);
+    const double dv = dv2 * rs;
     const double ss = gi.s + gj.s;
     const double K = M_PI * ss * ss * dv * (diag ? 0.5 : 1.0);
     double pf, pc;
