@@ -82,6 +82,9 @@ __device__ inline void heavier_terms(const CellRate &r, Grain &g, double S) {
 // r <- r (3/2 - x r^2 / 2), twice).  Within an ulp or two of the rounded
 // results, in fewer instructions than the IEEE sequences, which also scale
 // for denormal and overflowing operands.
+// exp(-y) rounds to zero in FP64 for y above about 745.13
+constexpr double kExpZeroY = 746.0;
+
 __device__ __forceinline__ double div_nr(double a, double b) {
     double r = __builtin_amdgcn_rcp(b);
     r = fma(fma(-b, r, 1.0), r, r);
@@ -119,13 +122,13 @@ __device__ inline void pair_rates(const CellRate &r, const Grain &gi, const Grai
     const double dv = dv2 * rs;
     const double ss = gi.s + gj.s;
     const double K = M_PI * ss * ss * dv * (diag ? 0.5 : 1.0);
-    double pf, pc;
-    if (!(dv2 > 0.0)) {
-        pf = 0.0;
-        pc = 1.0;
-    } else {
-        const double qv = r.vf * rs;
-        const double y = 1.5 * qv * qv;
+    // past y = kExpZeroY, exp(-y) is zero in FP64 (denormals included), so
+    // pf = 0 and pc = 1 exactly; pairs of slowly colliding grains, the most
+    // common, then skip the exponential (a branch whole waves take together)
+    double pf = 0.0, pc = 1.0;
+    const double qv = r.vf * rs;
+    const double y = 1.5 * qv * qv;
+    if (dv2 > 0.0 && y < kExpZeroY) {
         pf = (1.0 + y) * exp(-y);
         pc = y < kSeriesY
                  ? y * y * (1.0 / 2.0 + y * (-1.0 / 3.0 + y * (1.0 / 8.0 + y * (-1.0 / 30.0 +
