@@ -144,7 +144,7 @@ __device__ inline void pair_rates(const CellRate &r, const Grain &gi, const Grai
 // c % 16; cells past C get zeros), double or rounded to float, by NT threads
 // of a workgroup: thread t works on cell t % 16 and pairs t / 16 + (NT / 16) k,
 // so that the 16 cells of a pair leave as one run (64 bytes in FP32, a
-// 128-byte line in FP64).  Per-grain values in `lds` as [value][bin][cell]
+// 128-byte line in FP64).  Per-grain values in `lds` as [bin][value][cell]
 // (the lanes of a pair read 16 consecutive doubles).  TAB = 7 tabulates St, A,
 // B, C and the velocity; for grids whose 16 cells' values would not fit LDS
 // otherwise, TAB = 6 leaves out C and TAB = 1 keeps St only (the velocity then
@@ -165,7 +165,9 @@ __device__ void rates_block(const Tables &T, const CellArrays &cells,
     constexpr int SLOTS = NT / 16;
     const int N = T.N, P = T.P;
     double *tb = lds, *sv = lds + 16 * TAB * N, *imv = sv + N;
-    auto tab = [&](int v, int k, int cl) -> double & { return tb[(v * N + k) * 16 + cl]; };
+    // [bin][value][cell]: the values of one grain 128 bytes apart, so that
+    // a lane reads them all from one address with immediate offsets
+    auto tab = [&](int v, int k, int cl) -> double & { return tb[(k * TAB + v) * 16 + cl]; };
     for (int t = threadIdx.x; t < 16 * N; t += NT) {
         const int cl = t & 15, k = t >> 4;
         const long c = cell0 + cl;
