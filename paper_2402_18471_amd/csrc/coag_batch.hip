@@ -538,6 +538,9 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         // factor is applied once per block.
         constexpr int NJ = 4;
         auto jof = [&](int q, int u) { return 16 * q + 4 * g + u; };
+        // The sums restart with the first chunk of each block, which scales
+        // them by keep = 0 as it adds its own terms (later chunks: keep = 1),
+        // rather than clearing them in the branch that deposits them.
         double colsum[NJ], cratsum[NJ];
 #pragma unroll
         for (int u = 0; u < NJ; ++u) colsum[u] = cratsum[u] = 0.0;
@@ -550,8 +553,6 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                     atomicAdd(&netc[j], -mj * colsum[u]);
                     atomicAdd(&phic[fcol[j]], (1.0 + chi) * mj * cratsum[u]);
                 }
-                colsum[u] = 0.0;
-                cratsum[u] = 0.0;
             }
         };
         // n_j / max n of the lane's four lighter grains (zero past the grid)
@@ -604,11 +605,13 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             const int i = ci, q = cq;
             advance(ci, cq);
             load_b(ch + 1 < c1 ? ch + 1 : ch, bb[(u + 1) & 1]);
-            if (q != colq) {
+            const bool fresh = q != colq;
+            if (fresh) {
                 flush_cols(colq);
                 colq = q;
                 load_cols(q);
             }
+            const double keep = fresh ? 0.0 : 1.0;
             // x = n_j K / max n (FP32, the MFMA operand); the FP64 rate of
             // the pair for the column terms is (n_i max n) x.  Column terms:
             // the rate sums, and fragments (crater: summed for the block;
@@ -628,13 +631,14 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                     x[s] = ok ? njv[s] * (float)rk[u][s] : 0.0f;
                     x[4 + s] = ok ? njv[s] * (float)rk[u][4 + s] : 0.0f;
                     const double xf = (double)x[4 + s];
-                    colsum[s] = fma(c64, (double)x[s] + xf, colsum[s]);
+                    colsum[s] = fma(colsum[s], keep, c64 * ((double)x[s] + xf));
+                    const double rf = c64 * xf;
                     if (crat) {
-                        cratsum[s] = fma(c64, xf, cratsum[s]);
+                        cratsum[s] = fma(cratsum[s], keep, rf);
                     } else {
-                        const double mj = mk[jc], rf = c64 * xf;
+                        const double mj = mk[jc];
                         const bool crater = chi * mj < mi;
-                        cratsum[s] += crater ? rf : 0.0;
+                        cratsum[s] = fma(cratsum[s], keep, crater ? rf : 0.0);
                         dest += crater ? 0.0 : (mi + mj) * rf;
                     }
                 }
