@@ -179,6 +179,32 @@ def test_step_fixed_parity(O, case, kernel):
         np.testing.assert_array_equal(_np(r["h_log"])[:, :n], o["h_log"][:, :n])
 
 
+@pytest.mark.parametrize("chi", [2.0, 0.5])
+def test_batched_step_other_crater_yields(O, chi):
+    """The batched FP64 step with chi = 2 (destroyed targets below the
+    diagonal) and chi = 1/2 (every collision craters)."""
+    cfg, g, d, ctx, cells = _case(O, "disc256x128_n150", 8, 4, kernel="batch")
+    g.chi = chi
+    ctx = make_ctx(ctx.m, ctx.m_edge, ctx.s, "batch", rho_m=cfg.rho_m, chi=chi)
+    oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
+    C, n, dt = d["rho"].shape[0], 3, d["dt"] * 4
+    rho0 = d["rho"]
+
+    def blocked(K):
+        # [C][P] -> [ceil(C/16)][P][16]: a layout only the batched kernel takes
+        # (COAG_ENOTSUP, raised, if this grid and chi did not allow it)
+        b = np.zeros((-(-C // 16) * 16, K.shape[1]))
+        b[:C] = K
+        return _t(b.reshape(-1, 16, K.shape[1]).transpose(0, 2, 1))
+
+    r = ctx.coag_step(_t(rho0), blocked(oKc), blocked(oKf), dt, mode=1,
+                      nsub=_t(np.full(C, n), torch.int32), max_sub=8)
+    torch.cuda.synchronize()
+    o, env = _envelope(lambda x: O.step(g, x, oKc, oKf, dt, mode=O.FIXED, nsub=n)["rho"], rho0)
+    assert np.all(_np(r["status"]) == 0)
+    assert np.all(_step_tol(_np(r["rho"]), o, rho0, _gl_dt(O, g, rho0, oKc, oKf, dt), env))
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("case", [("disc64x32_n100", 16, 8, None),
                                   ("disc256x128_n150", 8, 4, None),

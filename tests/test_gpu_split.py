@@ -119,6 +119,30 @@ def test_split_step_replays_oracle_steps(O, case, rates):
         assert np.max(np.abs(x.sum(1) / rho0.sum(1) - 1)) <= 1e-12
 
 
+@pytest.mark.parametrize("chi", [2.0, 0.5])
+def test_split_step_other_crater_yields(O, chi):
+    """chi = 2: a projectile destroys targets up to twice its mass, so whole
+    chunks below the diagonal mix cratering and destroyed pairs; chi = 1/2:
+    every collision craters, the diagonal included."""
+    from paper_2402_18471_amd.coag import coag_create
+    cfg, g, d, ctx, cells = _case(O, "disc256x128_n150", 8, 4)
+    g.chi = chi
+    ctx = coag_create(ctx.m, ctx.m_edge, ctx.s, rho_m=cfg.rho_m, chi=chi)
+    oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
+    Kc, Kf = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]))
+    for rho0, dt in ((d["rho"], 20 * d["dt"]), (_evolved(O, g, d, oKc, oKf), d["dt"])):
+        o = O.step(g, rho0, oKc, oKf, dt, max_sub=512)
+        assert np.all(o["status"] == 0)
+        r = ctx.coag_step(_t(rho0), Kc, Kf, dt, mode=2, prec=1, nsub=_t(o["nsub"], torch.int32),
+                          h_log=_t(o["h_log"]))
+        torch.cuda.synchronize()
+        assert np.all(_np(r["status"]) == 0)
+        x = _np(r["rho"])
+        ok, worst = _bar(x, o["rho"], rho0)
+        assert np.all(ok), worst
+        assert np.max(np.abs(x.sum(1) / rho0.sum(1) - 1)) <= 1e-12
+
+
 @pytest.mark.parametrize("case", CASES[1:3])
 def test_split_adaptive_replayed_by_oracle(O, case):
     """ADAPTIVE split step; the oracle replays its accepted steps."""
