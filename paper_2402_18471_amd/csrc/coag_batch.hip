@@ -205,6 +205,11 @@ __device__ __forceinline__ double wave_min_d(double v) {
     return v;
 }
 
+// Row stride of the per-cell LDS arrays: odd, so that 16 cells' entries of
+// one bin fall in 16 different banks (a stride that is a multiple of 2^k
+// folds them onto 32 / 2^(k-1) banks: 8-way conflicts at N = 80, 4-way at 200)
+__host__ __device__ constexpr int batch_row_stride(int N) { return N | 1; }
+
 // The batch a workgroup takes.  Workgroups are dealt to the eight XCDs in
 // turn (workgroup w to XCD w mod 8), and each XCD runs its share from its own
 // queue, so with the plain mapping XCD x would take every batch b = x mod 8:
@@ -226,10 +231,14 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
     const long P = T.P;
     const long bt = batch_of(blockIdx.x, gridDim.x);
     const long cell0 = bt * kBC;
-    double *nv = lds, *net = lds + kBC * N, *phi = lds + 2 * kBC * N, *mk = lds + 3 * kBC * N;
+    // the per-cell rows of nv, net, phi and nf are NS = N | 1 elements apart:
+    // an odd stride puts the same bin of the 16 cells, which a chunk's lanes
+    // read and deposit together, in 16 different LDS banks for any N
+    const int NS = batch_row_stride(N);
+    double *nv = lds, *net = lds + kBC * NS, *phi = lds + 2 * kBC * NS, *mk = lds + 3 * kBC * NS;
     int *fcol = (int *)(mk + N), *frow = fcol + N, *wbl = frow + N;
-    float *nf = (float *)(fcol + 4 * N);          // split form: [16][N] n_k / max_k n_k
-    Ctl *ctl = (Ctl *)(lds + (3 * kBC + 3 + kBC / 2) * N);
+    float *nf = (float *)(fcol + 4 * N);          // split form: [16][NS] n_k / max_k n_k
+    Ctl *ctl = (Ctl *)(mk + 3 * N + kBC / 2 * NS);
     int *flag = (int *)(ctl + kBC);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -333,20 +342,20 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                         yn[k] = x;
                     }
                     const double n = x / mk[k];
-                    nv[c * N + k] = n;
+                    nv[c * NS + k] = n;
                     mx = fmax(mx, fabs(n));
                 }
             } else {
-                for (int k = lane; k < N; k += 64) nv[c * N + k] = 0.0;
+                for (int k = lane; k < N; k += 64) nv[c * NS + k] = 0.0;
             }
             for (int k = lane; k < N; k += 64) {
-                net[c * N + k] = 0.0;
-                phi[c * N + k] = 0.0;
+                net[c * NS + k] = 0.0;
+                phi[c * NS + k] = 0.0;
             }
             if (PREC == 1) {
                 mx = wave_max_d(mx);
                 const double inv = mx > 0.0 ? 1.0 / mx : 0.0;
-                for (int k = lane; k < N; k += 64) nf[c * N + k] = (float)(nv[c * N + k] * inv);
+                for (int k = lane; k < N; k += 64) nf[c * NS + k] = (float)(nv[c * NS + k] * inv);
                 if (lane == 0) {
                     ctl[c].nmax = mx;
                     ctl[c].inv_nmax = inv;
@@ -370,8 +379,8 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         const int NC = B.NC;
         const int c0 = (int)((long)wv * NC / kBWaves), c1 = (int)((long)(wv + 1) * NC / kBWaves);
         if (c0 >= c1) return;
-        const double *nrow = nv + cl * N;
-        double *netc = net + cl * N, *phic = phi + cl * N;
+        const double *nrow = nv + cl * NS;
+        double *netc = net + cl * NS, *phic = phi + cl * NS;
         const double chi = T.chi;
         // (i, q) -> (i, q + 1) or (i + 1, 0)
         auto advance = [](int &i, int &q) {
@@ -388,7 +397,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         auto flush = [&](int i) {
             const int bin = wbl[i] + cl;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) atomicAdd(&net[(g + 4 * r) * N + bin], acc64[r]);
+            for (int r = 0; r < 4; ++r) atomicAdd(&net[(g + 4 * r) * NS + bin], acc64[r]);
         };
         // the batch's rates: reordered in the workspace ([P][kind][16]), or the
         // caller's 16-cell-blocked arrays ([P][16] per kind)
@@ -502,10 +511,10 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         const int NC = B.NC;
         const int c0 = (int)((long)wv * NC / kBWaves), c1 = (int)((long)(wv + 1) * NC / kBWaves);
         if (c0 >= c1) return;
-        const double *nrow = nv + cl * N;
-        double *netc = net + cl * N, *phic = phi + cl * N;
+        const double *nrow = nv + cl * NS;
+        double *netc = net + cl * NS, *phic = phi + cl * NS;
         const double nmax = ctl[cl].nmax;
-        const float *nfr = nf + cl * N;
+        const float *nfr = nf + cl * NS;
         const double chi = T.chi;
         // (i, q) -> (i + 1, q), or the top of the next column block
         auto advance = [N](int &i, int &q) {
@@ -525,8 +534,8 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int c = 4 * g + r;
-                const double f = nv[c * N + i] * ctl[c].nmax;
-                atomicAdd(&net[c * N + bin], f * (double)acc32[t][r]);
+                const double f = nv[c * NS + i] * ctl[c].nmax;
+                atomicAdd(&net[c * NS + bin], f * (double)acc32[t][r]);
             }
             acc32[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         };
@@ -703,13 +712,13 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             double carry = 0.0;
             for (int top = N - 1; top >= 0; top -= 64) {
                 const int k = top - lane;
-                double x = k >= 0 ? phi[c * N + k] * T.invE[k] : 0.0;
+                double x = k >= 0 ? phi[c * NS + k] * T.invE[k] : 0.0;
 #pragma unroll
                 for (int o = 1; o < 64; o <<= 1) {
                     const double y = __shfl_up(x, o, 64);
                     if (lane >= o) x += y;
                 }
-                if (k >= 0) out[k] = net[c * N + k] + T.dE[k] * (x + carry);
+                if (k >= 0) out[k] = net[c * NS + k] + T.dE[k] * (x + carry);
                 carry += __shfl(x, 63, 64);
             }
         }
@@ -853,7 +862,8 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
 }
 
 size_t batch_lds_bytes(int N) {
-    return (size_t)(3 * kBC + 3 + kBC / 2) * N * sizeof(double) + kBC * sizeof(Ctl) + 64;
+    return ((size_t)(3 * kBC + kBC / 2) * batch_row_stride(N) + 3 * N) * sizeof(double) +
+           kBC * sizeof(Ctl) + 64;
 }
 
 template <typename K>
