@@ -352,16 +352,51 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
         return fail(ctx, COAG_EINVAL, "coag_step_backward: NULL array");
     if (int r = set_device(ctx)) return r;
     const size_t P = ctx->P, N = ctx->N;
-    const size_t bK = align256(8 * P * (size_t)C);
+    // The forward replay that keeps the step-start and stage states runs on
+    // the batched step (REPLAY) where that applies, else inside k_adjoint.
+    // The batched replay works on a copy of rho_in, with its slopes and
+    // status after the adjoint's arrays, and reorders the [C][P] rates in the
+    // dJ/dK area, which k_adjoint clears before it accumulates there (so the
+    // rate arrays are sized for whole 16-cell batches).
+    const bool batched = ctx->batch_fp64 && batch_available(ctx->T, ctx->B);
+    const size_t Cb = ((size_t)C + kBatchCells - 1) / kBatchCells * kBatchCells;
+    const size_t bK = align256(8 * P * Cb);
     const size_t bY = align256(8 * N * (size_t)(log_stride + 1) * (size_t)C);
     const size_t bZ = align256(8 * N * 2 * (size_t)log_stride * (size_t)C);
-    if (int r = ensure_ws(ctx, 4 * bK + bY + bZ)) return r;
+    const size_t bR = batched ? align256(8 * N * (size_t)C) : 0;
+    const size_t bW = batched ? align256(batch_ws_bytes(ctx->N, C, 0, COAG_RATES_BLK64)) : 0;
+    const size_t bS = batched ? align256(4 * (size_t)C) : 0;
+    if (int r = ensure_ws(ctx, 4 * bK + bY + bZ + bR + bW + bS)) return r;
     char *w = (char *)ctx->ws;
     double *Kc = (double *)w, *Kf = (double *)(w + bK), *gKc = (double *)(w + 2 * bK),
            *gKf = (double *)(w + 3 * bK), *Ys = (double *)(w + 4 * bK);
+    double *Zs = (double *)(w + 4 * bK + bY);
     const CellArrays ca = cell_arrays(cells);
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(ctx, launch_rates(ctx->T, C, ca, v_dust, v_frag, Kc, Kf, st));
+    if (batched) {
+        char *wb = w + 4 * bK + bY + bZ;
+        double *y = (double *)wb;
+        HIP_TRY(ctx, hipMemcpyAsync(y, rho_in, 8 * N * (size_t)C, hipMemcpyDeviceToDevice, st));
+        StepArgs sa;
+        sa.rho = y;
+        sa.Kc = Kc;
+        sa.Kf = Kf;
+        sa.dt = 0.0;
+        sa.h = nullptr;
+        sa.rtol = sa.atol_rel = sa.h_min_rel = 0.0;
+        sa.max_sub = log_stride;
+        sa.mode = COAG_REPLAY;
+        sa.renorm = 0;
+        sa.nsub = const_cast<int32_t *>(nsub);       // read only in REPLAY
+        sa.nrej = nullptr;
+        sa.status = (int32_t *)(wb + bR + bW);
+        sa.h_log = const_cast<double *>(h_log);      // read only in REPLAY
+        sa.Ys = Ys;
+        sa.Zs = Zs;
+        HIP_TRY(ctx, launch_step_batch(ctx->T, ctx->B, C, sa, 0, COAG_RATES_CP64,
+                                       (double *)(wb + bR), st, gKc));
+    }
     AdjArgs a;
     a.rho_in = rho_in;
     a.Kc = Kc;
@@ -369,7 +404,8 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
     a.gKc = gKc;
     a.gKf = gKf;
     a.Ys = Ys;
-    a.Zs = (double *)(w + 4 * bK + bY);
+    a.Zs = Zs;
+    a.replayed = batched ? 1 : 0;
     a.h_log = h_log;
     a.log_stride = log_stride;
     a.nsub = nsub;

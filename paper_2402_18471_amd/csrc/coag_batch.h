@@ -44,7 +44,10 @@ size_t batch_ws_bytes(int N, long C, int prec, int layout);
 // prec: 0 = FP64 MFMA, 1 = split BF16.  layout of Kc / Kf: 0 = double [C][P],
 // 1 = float 16-cell-blocked (split only), 2 = double 16-cell-blocked (FP64
 // only); hipErrorNotSupported for other combinations
+// ws: batch_ws_bytes(N, C, prec, layout) bytes, or, with wk given, the
+// slope part only and wk the [C][P] reordering area (FP64 [C][P] rates)
 hipError_t launch_step_batch(const Tables &T, const BatchTables &B, long C, const StepArgs &a,
-                             int prec, int layout, double *ws, hipStream_t st);
+                             int prec, int layout, double *ws, hipStream_t st,
+                             void *wk = nullptr);
 
 }  // namespace coag

@@ -291,6 +291,9 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         double ms = 0.0;
         if (live)
             for (int k = lane; k < N; k += 64) ms += a.rho[gc * N + k];
+        if (live && a.Ys)
+            for (int k = lane; k < N; k += 64)
+                a.Ys[gc * (a.max_sub + 1L) * N + k] = a.rho[gc * N + k];
         ms = wave_sum_d(ms);
         if (lane == 0) {
             Ctl &s = ctl[c];
@@ -332,6 +335,10 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                 const double *y = a.rho + gc * N;
                 const double *k1 = wsp(c, 0), *k2 = wsp(c, 1), *k3 = wsp(c, 2);
                 double *yn = wsp(c, 4);
+                // REPLAY with kept stages: y2, y3 of sub-step nacc
+                double *zs = a.Zs && (stage == 2 || stage == 3)
+                                 ? a.Zs + ((gc * a.max_sub + ctl[c].nacc) * 2 + (stage - 2)) * (long)N
+                                 : nullptr;
                 for (int k = lane; k < N; k += 64) {
                     double x;
                     if (stage == 0) x = y[k];
@@ -341,6 +348,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                         x = y[k] + hh * (2.0 / 9.0 * k1[k] + 1.0 / 3.0 * k2[k] + 4.0 / 9.0 * k3[k]);
                         yn[k] = x;
                     }
+                    if (zs) zs[k] = x;
                     const double n = x / mk[k];
                     nv[c * NS + k] = n;
                     mx = fmax(mx, fabs(n));
@@ -783,6 +791,10 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         }
         if (accept) {
             for (int k = lane; k < N; k += 64) y[k] = yn[k];
+            if (a.Ys) {
+                double *ys = a.Ys + (gc * (a.max_sub + 1L) + s.nacc + 1) * N;
+                for (int k = lane; k < N; k += 64) ys[k] = yn[k];
+            }
             double *k1w = wsp(c, 0);
             for (int k = lane; k < N; k += 64) k1w[k] = k4[k];
             if (lane == 0) {
@@ -945,16 +957,17 @@ size_t batch_ws_bytes(int N, long C, int prec, int layout) {
 }
 
 hipError_t launch_step_batch(const Tables &T, const BatchTables &B, long C, const StepArgs &a,
-                             int prec, int layout, double *ws, hipStream_t st) {
+                             int prec, int layout, double *ws, hipStream_t st, void *wk) {
     if (C == 0) return hipSuccess;
     if (!batch_available(T, B)) return hipErrorNotSupported;
     const size_t bytes = batch_lds_bytes(T.N);
     const dim3 grid((unsigned)((C + kBC - 1) / kBC)), block(kBBlock);
+    char *wkp = wk ? (char *)wk : (char *)ws + slope_bytes(T.N, C);
 #define LAUNCH(PR, RT, BL)                                                                   \
     do {                                                                                     \
         if (hipError_t e = allow_lds_b(k_step_batch<PR, RT, BL>, bytes)) return e;          \
         hipLaunchKernelGGL((k_step_batch<PR, RT, BL>), grid, block, bytes, st, T, B, a, C,  \
-                           ws, (RT *)((char *)ws + slope_bytes(T.N, C)));                    \
+                           ws, (RT *)wkp);                                                   \
     } while (0)
     if (prec == 0 && layout == 0) LAUNCH(0, double, false);
     else if (prec == 0 && layout == 2) LAUNCH(0, double, true);

@@ -385,9 +385,10 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Tables T, AdjArgs a) {
         gKc[p] = 0.0;
         gKf[p] = 0.0;
     }
-    for (int k = threadIdx.x; k < N; k += BLOCK) Ys[k] = a.rho_in[c * N + k];
+    if (!a.replayed)
+        for (int k = threadIdx.x; k < N; k += BLOCK) Ys[k] = a.rho_in[c * N + k];
     __syncthreads();
-    for (int s = 0; s < n; ++s) {                     // forward replay
+    for (int s = 0; s < (a.replayed ? 0 : n); ++s) {  // forward replay
         const double *y = Ys + (long)s * N;
         double *yn = Ys + (long)(s + 1) * N;
         double *y2 = Zs + (long)s * 2 * N, *y3 = y2 + N;

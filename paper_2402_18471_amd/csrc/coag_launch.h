@@ -22,6 +22,10 @@ struct StepArgs {
     int max_sub, mode, renorm;
     int32_t *nsub, *nrej, *status;
     double *h_log;
+    // REPLAY on the batched step only: where to keep the step-start states
+    // and the inner stage states y2, y3 of every sub-step, laid out as
+    // AdjArgs::Ys and AdjArgs::Zs with log_stride = max_sub; nullptr: not kept
+    double *Ys = nullptr, *Zs = nullptr;
 };
 
 struct AdjArgs {
@@ -35,6 +39,7 @@ struct AdjArgs {
     const int32_t *nsub;
     const double *g_out;
     double *g_in;
+    int replayed = 0;            // Ys, Zs already hold the forward replay
 };
 
 hipError_t launch_build(int N, const double *m, const double *me, double eta, double chi,
