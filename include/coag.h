@@ -230,7 +230,8 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void 
      g_vfrag [C]    DEVICE out   dJ/dv_frag,c (through p_frag)
    Inputs rho_in [C][N], cells, v_dust, v_frag as for coag_rates; h_log
    [C][log_stride], nsub [C] DEVICE.  The stage states are recomputed from
-   rho_in.  prec: COAG_PREC_FP64 (the adjoint runs in FP64 only;
+   rho_in (by the batched step in REPLAY mode where that step applies) and
+   kept in the context's workspace for the reverse sweep.  prec: COAG_PREC_FP64 (the adjoint runs in FP64 only;
    COAG_PREC_SPLIT_BF16 returns COAG_ENOTSUP).  Errors: COAG_EINVAL,
    COAG_ENOTSUP, COAG_ENOMEM. */
 int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coag_cells *cells,
