@@ -279,17 +279,22 @@ def test_host_errors_leave_outputs_untouched(O):
     assert torch.equal(rho, before)
 
 
-def test_backward_parity(O):
-    """Adjoint on a well-conditioned grid (3 decades of mass): GPU vs oracle."""
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("cells_rz", [(4, 2), (5, 7)])
+def test_backward_parity(O, kernel, cells_rz):
+    """Adjoint on a well-conditioned grid (3 decades of mass): GPU vs oracle,
+    with the forward replay on the batched step (REPLAY mode, keeping the
+    stage states) or inside the adjoint kernel (per-cell contexts); 8 cells
+    (one partial batch of 16) and 35 (two whole batches and a ragged one)."""
     from paper_2402_18471_amd import disc
-    from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
-    cfg = disc.scaled(disc.CONFIGS["disc64x32_n100"], 4, 2, 24)
+    from paper_2402_18471_amd.coag import coag_mass_grid
+    cfg = disc.scaled(disc.CONFIGS["disc64x32_n100"], *cells_rz, 24)
     m, me, s = coag_mass_grid(24, 3e-4, 3e-3, rho_m=cfg.rho_m)
     g = O.make_grid(24, 3e-4, 3e-3, rho_m=cfg.rho_m)
     d = disc.make_disc(cfg, g.s)
     rng = np.random.default_rng(9)
     rho = 0.01 * d["cells"]["rho_g"][:, None] * rng.uniform(0.2, 1.0, (cfg.n_cells, g.N)) / g.N
-    ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
+    ctx = make_ctx(m, me, s, kernel, rho_m=cfg.rho_m)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
     a = O.step(g, rho, oKc, oKf, d["dt"] * 5, max_sub=32)
     g_out = rng.normal(size=rho.shape) / rho.sum(1, keepdims=True)
