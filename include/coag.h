@@ -125,7 +125,7 @@ typedef struct {
    edges are lo and hi (grain radius in cm if by_mass == 0, else mass in g),
    edges lo (hi/lo)^(k/N), centres at the log midpoints lo (hi/lo)^((k+1/2)/N),
    m = (4 pi / 3) rho_m s^3.  Writes m[N], m_edge[N+1], s[N] (HOST, caller-
-   owned).  Reading of Sec. 8: with it, the paper's 100 bins over
+   owned).  Reading of Sec. 7: with it, the paper's 100 bins over
    0.1 um - 0.5 cm and 135 bins over 0.1 um - 20 cm both have
    m_{n+1}/m_n = 1.38.  Returns COAG_EINVAL for N < 2, lo <= 0, hi <= lo,
    rho_m <= 0 or a null pointer. */

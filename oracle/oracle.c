@@ -37,7 +37,7 @@
 #undef EXPT
 
 /* ------------------------------------------------------------------------- */
-/* Mass grid (Sec. 8: log-spaced bins with a fixed ratio m_{n+1}/m_n).       */
+/* Mass grid (Sec. 7: log-spaced bins with a fixed ratio m_{n+1}/m_n).       */
 /* The quoted size range is taken as the outer bin edges: N bins log-spaced  */
 /* in radius (by_mass = 0, lo/hi in cm) or in mass (by_mass = 1, lo/hi in g) */
 /* with edges x_k = lo (hi/lo)^(k/N), k = 0..N, and centres at the log       */

@@ -88,6 +88,25 @@ def header_symbols():
     return sorted(set(re.findall(r"\b(coag_[a-z0-9_]+)\s*\(", src)))
 
 
+class CoagCellError(CoagError):
+    """Some cells of a coag_step call did not complete (per-cell status)."""
+
+    def __init__(self, counts):
+        names = {CELL_HMIN: "HMIN", CELL_MAXSUB: "MAXSUB", CELL_NONFINITE: "NONFINITE"}
+        what = ", ".join(f"{n} {names.get(k, k)}" for k, n in sorted(counts.items()))
+        super().__init__(0, f"coag_step: cells failed ({what})")
+        self.counts = counts
+
+
+def check_cells(status):
+    """Raise CoagCellError if any entry of the per-cell status tensor is not
+    CELL_OK (waits for the stream that wrote it)."""
+    bad = status[status != CELL_OK]
+    if bad.numel():
+        vals, cnt = bad.unique(return_counts=True)
+        raise CoagCellError({int(v): int(c) for v, c in zip(vals.tolist(), cnt.tolist())})
+
+
 def check(rc, ctx=None):
     if rc != COAG_OK:
         msg = load().coag_last_error(ctx)

@@ -128,11 +128,14 @@ class CoagContext:
 
     def coag_step(self, rho, Kc, Kf, dt, h=None, mode=L.ADAPTIVE, prec=L.PREC_FP64, rtol=1e-2,
                   atol_rel=1e-10, h_min_rel=1e-12, max_sub=10000, renorm=False, nsub=None,
-                  h_log=None, log=True):
+                  h_log=None, log=True, check_status=True):
         """Advances rho (in place) by dt; returns dict(rho, h, nsub, nrej, h_log, status).
         Kc, Kf: float64 [C][P] from coag_rates, or the 16-cell-blocked rates
         of coag_rates_blocked (float32: split precision only; float64: FP64
-        only)."""
+        only).  check_status: wait for the call and raise CoagCellError if any
+        cell's status is not COAG_CELL_OK (the failed cells keep the state
+        the call left them in); False returns at once, with the per-cell
+        status for the caller to inspect."""
         C = int(rho.shape[0])
         dev = rho.device
         _dev(rho, shape=(C, self.N), name="rho")
@@ -163,7 +166,10 @@ class CoagContext:
         self._check(self._lib.coag_step(self._h, C, _ptr(rho), _ptr(Kc), _ptr(Kf), float(dt),
                                         _ptr(h), ct.byref(tol), _ptr(nsub), _ptr(nrej),
                                         _ptr(h_log), _ptr(status), _stream()))
-        return dict(rho=rho, h=h, nsub=nsub, nrej=nrej, h_log=h_log, status=status)
+        out = dict(rho=rho, h=h, nsub=nsub, nrej=nrej, h_log=h_log, status=status)
+        if check_status:
+            L.check_cells(status)
+        return out
 
     def coag_step_backward(self, rho_in, cells, v_dust, v_frag, h_log, nsub, g_out,
                            prec=L.PREC_FP64):

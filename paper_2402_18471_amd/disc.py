@@ -6,7 +6,7 @@ initial size distribution.  It contains none of the coagulation method's
 arithmetic, and it is the only code that the GPU library's tests and the CPU
 oracle's tests both use.
 
-Disc shape follows the paper's transition-disc test (Sec. 8, table `params`):
+Disc shape follows the paper's transition-disc test (Sec. 7, table `params`):
 Sigma_g = Sigma_0 R_au^-1 exp[-(5/R_au)^10], Sigma_0 = 250 g cm^-2, M_* = 1 M_sun,
 mu = 2.4; vertically isothermal T = 150 K (R/au)^-1/2; Gaussian rho_g(Z) with
 H/R = 0.05; MRN initial dust (n(s) ~ s^-3.5) up to 1 micron at dust-to-gas 0.01.

@@ -83,7 +83,7 @@ def test_odd_cells_in_a_batch(O, form, shape):
         nsub[4] = 99                                  # more than max_sub
     dt = d["dt"]
     r = ctx.coag_step(_t(rho0), _t(Kc), _t(Kf), dt, mode=1, prec=prec, nsub=_t(nsub, torch.int32),
-                      max_sub=8)
+                      max_sub=8, check_status=False)
     torch.cuda.synchronize()
     st, x = _np(r["status"]), _np(r["rho"])
     assert st[0] == 0 and np.all(x[0] == 0.0)

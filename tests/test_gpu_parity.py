@@ -242,7 +242,7 @@ def test_step_renorm_and_status(O, kernel):
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
     rho0 = d["rho"].copy()
     rho0[1, 5] = np.nan
-    r = ctx.coag_step(_t(rho0), _t(oKc), _t(oKf), d["dt"], renorm=True)
+    r = ctx.coag_step(_t(rho0), _t(oKc), _t(oKf), d["dt"], renorm=True, check_status=False)
     torch.cuda.synchronize()
     st = _np(r["status"])
     assert st[1] == 3 and np.all(np.delete(st, 1) == 0)
@@ -250,9 +250,14 @@ def test_step_renorm_and_status(O, kernel):
     m0, m1 = rho0[ok].sum(1), _np(r["rho"])[ok].sum(1)
     assert np.max(np.abs(m1 / m0 - 1)) < 1e-15
     # max_sub exhausted
-    r = ctx.coag_step(_t(d["rho"]), _t(oKc), _t(oKf), d["dt"] * 1e4, max_sub=2)
+    r = ctx.coag_step(_t(d["rho"]), _t(oKc), _t(oKf), d["dt"] * 1e4, max_sub=2, check_status=False)
     torch.cuda.synchronize()
     assert np.any(_np(r["status"]) == 2)
+    # by default the binding raises on the failed cells
+    from paper_2402_18471_amd import _lib as L
+    with pytest.raises(L.CoagCellError) as ei:
+        ctx.coag_step(_t(d["rho"]), _t(oKc), _t(oKf), d["dt"] * 1e4, max_sub=2)
+    assert ei.value.counts.get(L.CELL_MAXSUB, 0) > 0
 
 
 def test_zero_cells_is_a_no_op(O):

@@ -188,3 +188,104 @@ def test_rates_nonnegative_and_finite_on_disc(O):
     Kc, Kf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
     assert np.all(np.isfinite(Kc)) and np.all(np.isfinite(Kf))
     assert np.all(Kc >= 0) and np.all(Kf >= 0) and np.all(Kc + Kf > 0)
+
+
+# A cell whose gas state has no unit values and no two equal ones, so that a
+# factor put in the wrong place (rho_m for rho_g, Omega divided instead of
+# multiplied, c_s missing from v_th, H missing from Re) changes the Stokes or
+# Reynolds number by orders of magnitude.
+_RHO_M, _RHO_G, _OMEGA, _C_S, _H = 3.3, 2.1e-2, 0.13, 23.0, 2.3
+
+
+def _physical_cell(alpha, Re):
+    """One cell with the distinct values above; nu_mol set so that
+    Re = alpha c_s H / nu_mol (Sec. 7.1) takes the requested value."""
+    nu = alpha * _C_S * _H / Re
+    one = np.ones(1)
+    return dict(T=0.0 * one, rho_g=_RHO_G * one, c_s=_C_S * one, Omega=_OMEGA * one,
+                H=_H * one, nu_mol=nu * one, alpha=alpha * one)
+
+
+def _stokes(s):
+    """St = t_s Omega with the Epstein stopping time of eq. `t_stop` (Sec. 3.1),
+    t_s = rho_m s / (rho_g v_th), v_th = (8/pi)^1/2 c_s; written out here,
+    independently of the oracle."""
+    v_th = np.sqrt(8.0 / np.pi) * _C_S
+    return _RHO_M * s / (_RHO_G * v_th) * _OMEGA
+
+
+def _grid_for_stokes(O, st_lo, st_hi, N=16):
+    """Grid whose bins span the Stokes numbers [st_lo, st_hi] in the cell above."""
+    per_cm = _stokes(1.0)
+    m, me, s = O.mass_grid(N, st_lo / per_cm, st_hi / per_cm, rho_m=_RHO_M)
+    return O.Grid(m, me, s, _RHO_M)
+
+
+def _vrel2_physical(O, g, alpha, Re):
+    """V_rel^2 recovered from K (T = 0, no laminar motion, v_frag = 0 so that
+    every collision fragments and K = w sigma sqrt(alpha) c_s V_rel)."""
+    cells = _physical_cell(alpha, Re)
+    Kc, Kf = O.rates(g, cells, np.zeros((1, g.N, 3)), 0.0)
+    assert np.all(Kc == 0)
+    out = {}
+    for i in range(g.N):
+        for j in range(i + 1):
+            p = i * (i + 1) // 2 + j
+            w = 0.5 if i == j else 1.0
+            dv = Kf[0, p] / (w * np.pi * (g.s[i] + g.s[j]) ** 2)
+            out[(i, j)] = dv * dv / (alpha * _C_S ** 2)
+    return out
+
+
+def test_stokes_and_reynolds_numbers_in_a_physical_cell(O):
+    """The Ormel & Cuzzi limits at Stokes and Reynolds numbers computed here
+    from the cell's rho_m, rho_g, Omega, c_s, H and nu_mol (eq. `t_stop`,
+    Re = nu_t / nu_mol with nu_t = alpha c_s H): tiny grains give
+    V_rel^2 -> Re^1/2 (St_1 - St_2)^2, equal intermediate grains
+    V_rel^2 -> (2 y* - 2 + 2/(1 + y*)) St, heavy grains 1/(1+St_1) + 1/(1+St_2).
+    Swapping rho_m and rho_g, or dropping c_s, Omega or H, moves St or Re by
+    a factor of 10 or more and fails these by far more than their tolerance."""
+    alpha = 2.7e-3
+    # tiny: St << Re^-1/2 (Re = 1e8, delta = 1e-4)
+    Re = 1e8
+    delta = Re ** -0.5
+    g = _grid_for_stokes(O, 1e-6 * delta, 1e-3 * delta)
+    st = _stokes(g.s)
+    v = _vrel2_physical(O, g, alpha, Re)
+    for (i, j), val in v.items():
+        if i != j:
+            np.testing.assert_allclose(val, (st[i] - st[j]) ** 2 / delta, rtol=3e-3)
+    # intermediate, equal sizes: delta << St << 1 (Re = 1e14)
+    Re = 1e14
+    g = _grid_for_stokes(O, 1e-4, 1e-2)
+    st = _stokes(g.s)
+    v = _vrel2_physical(O, g, alpha, Re)
+    coef = 2 * YSTAR - 2 + 2 / (1 + YSTAR)
+    for i in range(g.N):
+        np.testing.assert_allclose(v[(i, i)], coef * st[i], rtol=1e-5)
+    # heavy: St >> 1
+    g = _grid_for_stokes(O, 1e2, 1e5)
+    st = _stokes(g.s)
+    v = _vrel2_physical(O, g, alpha, Re)
+    for (i, j), val in v.items():
+        np.testing.assert_allclose(val, 1 / (1 + st[i]) + 1 / (1 + st[j]), rtol=1e-6)
+    # the chosen values really separate the factors: each misplacement moves
+    # St by at least a factor 10
+    base = _stokes(1.0)
+    v_th = np.sqrt(8 / np.pi) * _C_S
+    for wrong in (_RHO_G * 1.0 / (_RHO_M * v_th) * _OMEGA,      # rho_m <-> rho_g
+                  _RHO_M / (_RHO_G * v_th) / _OMEGA,              # Omega divided
+                  _RHO_M / (_RHO_G * np.sqrt(8 / np.pi)) * _OMEGA):  # c_s dropped
+        assert max(wrong / base, base / wrong) > 10
+
+
+def test_reynolds_number_sets_the_smallest_eddy(O):
+    """Tiny-grain limit at two Reynolds numbers 100 apart in the same cell
+    (only nu_mol changes): V_rel^2 scales as Re^1/2, i.e. by 10."""
+    alpha = 2.7e-3
+    g = _grid_for_stokes(O, 1e-12, 1e-9)
+    a = _vrel2_physical(O, g, alpha, 1e8)
+    b = _vrel2_physical(O, g, alpha, 1e10)
+    for key in a:
+        if key[0] != key[1]:
+            np.testing.assert_allclose(b[key] / a[key], 10.0, rtol=1e-3)

@@ -1,5 +1,5 @@
 """Pins of the oracle's mass grid and redistribution tables (Sec. 5, eqs.
-`Cijk`, `Rijk`, `fragdist`, `Nijk`, `fragrem`; grid of Sec. 8).
+`Cijk`, `Rijk`, `fragdist`, `Nijk`, `fragrem`; grid of Sec. 7).
 
 Each check compares the oracle with something other than itself: numbers the
 paper prints, exact invariants of the two-bin split, numerical integration of
@@ -19,7 +19,7 @@ def _pairs(N):
 
 
 def test_paper_grid_ratio(O):
-    """Sec. 8: 100 bins over 0.1 um - 0.5 cm and 135 over 0.1 um - 20 cm both
+    """Sec. 7: 100 bins over 0.1 um - 0.5 cm and 135 over 0.1 um - 20 cm both
     give m_{n+1}/m_n = 1.38 (printed to two decimals)."""
     rows = [l.split() for l in open(os.path.join(GOLDEN, "paper_grid_ratio.txt"))
             if l.strip() and not l.startswith("#")]
