@@ -14,7 +14,7 @@ Measured on the 256x128-cell, 150-bin disc:
                  FP64 path, and its per-bin error against the FP64 GPU path
                  (replaying the same steps) on a stratified sample of cells
   adjoint        coag_step_backward time over forward (rates + step) time on
-                 the 64x32-cell, 100-bin disc
+                 the 64x32-cell, 100-bin disc, FP64 and split BF16
   roofline       the FP64 step kernel against HBM bandwidth: algorithmic
                  bytes = (16 P + 16 N) per cell per right-hand side
   cpu_baseline   the CPU oracle on a sample of the same workload
@@ -354,34 +354,46 @@ def split_error(D, rho_start, sample):
 
 def adjoint_ratio(torch, reps=3):
     """Backward / forward time of the same coagulation call on the 64x32 x 100
-    adjoint disc: the first call from the initial state (rates + ADAPTIVE
-    step, steps recorded), then coag_step_backward of that call (which
-    recomputes the rates and the stage states); HIP events on the stream,
-    mean over reps after one warm-up."""
+    adjoint disc, in FP64 and in split BF16: the first call from the initial
+    state (rates + ADAPTIVE step, steps recorded; the split form with FP32
+    blocked rates), then coag_step_backward of that call in the same
+    precision (which recomputes the rates and their derivative factors and
+    replays the stage states); HIP events on the stream, mean over reps after
+    one warm-up."""
+    from paper_2402_18471_amd import _lib as L
     D = Disc("disc64x32_n100_adj", torch)
     rho_in = D.t(D.d["rho"])
     dt = float(D.d["dt"])
     g_out = torch.ones((D.C, D.N), dtype=torch.float64, device=D.dev) / rho_in.sum(1, keepdim=True)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    fwd, bwd = [], []
-    for r in range(reps + 1):
-        rho = rho_in.clone()
-        ev[0].record(D.stream)
-        Kc, Kf = D.ctx.coag_rates(D.cells, D.v_dust, D.v_frag)
-        a = D.ctx.coag_step(rho, Kc, Kf, dt, max_sub=64)
-        ev[1].record(D.stream)
-        ev[2].record(D.stream)
-        D.ctx.coag_step_backward(rho_in, D.cells, D.v_dust, D.v_frag, a["h_log"], a["nsub"], g_out)
-        ev[3].record(D.stream)
-        torch.cuda.synchronize()
-        if r:
-            fwd.append(ev[0].elapsed_time(ev[1]))
-            bwd.append(ev[2].elapsed_time(ev[3]))
-    f, b = float(np.mean(fwd)), float(np.mean(bwd))
-    return {"workload": D.cfg.name, "backward_ms": b, "forward_ms": f, "adjoint_over_forward": b / f,
-            "note": "same call both ways: the first call from the initial state, "
-                    f"{float(a['nsub'].float().mean()):.2f} accepted sub-steps per cell; forward = "
-                    "rates + ADAPTIVE step; backward recomputes rates and stage states"}
+    out = {"workload": D.cfg.name}
+    for name, prec in (("fp64", L.PREC_FP64), ("split_bf16", L.PREC_SPLIT_BF16)):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        fwd, bwd = [], []
+        for r in range(reps + 1):
+            rho = rho_in.clone()
+            ev[0].record(D.stream)
+            if prec == L.PREC_SPLIT_BF16:
+                Kc, Kf = D.ctx.coag_rates_blocked(D.cells, D.v_dust, D.v_frag)
+            else:
+                Kc, Kf = D.ctx.coag_rates(D.cells, D.v_dust, D.v_frag)
+            a = D.ctx.coag_step(rho, Kc, Kf, dt, max_sub=64, prec=prec, check_status=False)
+            ev[1].record(D.stream)
+            ev[2].record(D.stream)
+            D.ctx.coag_step_backward(rho_in, D.cells, D.v_dust, D.v_frag, a["h_log"], a["nsub"],
+                                     g_out, prec=prec)
+            ev[3].record(D.stream)
+            torch.cuda.synchronize()
+            L.check_cells(a["status"])
+            if r:
+                fwd.append(ev[0].elapsed_time(ev[1]))
+                bwd.append(ev[2].elapsed_time(ev[3]))
+        f, b = float(np.mean(fwd)), float(np.mean(bwd))
+        out[name] = {"backward_ms": b, "forward_ms": f, "adjoint_over_forward": b / f,
+                     "accepted_substeps_per_cell": float(a["nsub"].float().mean())}
+    out["note"] = ("same call both ways: the first call from the initial state; forward = rates "
+                   "+ ADAPTIVE step; backward recomputes the rates, their derivative factors and "
+                   "the stage states, then runs the reverse sweep")
+    return out
 
 
 def main():

@@ -3,21 +3,31 @@ hand-written adjoint of libcoag (coag_step_backward) as its backward.
 
 Forward: n_steps calls of coag_rates + coag_step (ADAPTIVE, or FIXED with
 `fixed_nsub` equal sub-steps per call), recording each call's accepted step
-sizes and keeping the state every `ckpt_every` calls.
+sizes and keeping the state every `ckpt_every` calls.  The split-BF16 form
+takes FP32 rates in the 16-cell-blocked layout, as its step streams them.
 Backward: for each checkpoint segment, from the last to the first, the
 segment is recomputed from its checkpoint with the recorded step sizes
 (REPLAY, so the step sequence is exactly the one the forward pass took) and
-the adjoint runs through its calls in reverse.  Gradients are returned for the
-initial density, alpha and v_frag (per cell); the other inputs are not
-differentiated.  The adjoint is FP64: after a split-precision forward pass it
-differentiates the FP64 map along the split trajectory (the recomputation
-replays the split steps, the adjoint its own FP64 stages).
+the adjoint runs through its calls in reverse, in the forward's precision:
+FP64, or split BF16 (the transposed gain contraction as split-BF16 matrix
+products, everything else FP64).  Gradients are returned for the initial
+density, alpha and v_frag (per cell); the other inputs are not
+differentiated.  Each call's step log is kept only as wide as its longest
+step sequence.
 """
 from __future__ import annotations
 
 import torch
 
 from . import _lib as L
+
+
+def _rates(coag, cells, v_dust, vf, prec):
+    """The rates one call's step reads: FP32, 16-cell-blocked for the split
+    form; FP64 [C][P] for the FP64 form."""
+    if prec == L.PREC_SPLIT_BF16:
+        return coag.coag_rates_blocked(cells, v_dust, vf, dtype=torch.float32)
+    return coag.coag_rates(cells, v_dust, vf)
 
 
 class CoagStep(torch.autograd.Function):
@@ -31,9 +41,8 @@ class CoagStep(torch.autograd.Function):
         vf = v_frag.detach().contiguous()
         rho = rho0.detach().clone()
         h = torch.zeros(C, dtype=torch.float64, device=dev)
-        logs = torch.zeros((n_steps, C, max_sub), dtype=torch.float64, device=dev)
-        nsubs = torch.zeros((n_steps, C), dtype=torch.int32, device=dev)
-        ckpts = []
+        log = torch.zeros((C, max_sub), dtype=torch.float64, device=dev)
+        logs, nsubs, ckpts = [], torch.zeros((n_steps, C), dtype=torch.int32, device=dev), []
         mode = L.ADAPTIVE if fixed_nsub is None else L.FIXED
         if fixed_nsub is not None:
             if not 1 <= int(fixed_nsub) <= max_sub:
@@ -42,14 +51,17 @@ class CoagStep(torch.autograd.Function):
         for s in range(n_steps):
             if s % ckpt_every == 0:
                 ckpts.append(rho.clone())
-            Kc, Kf = coag.coag_rates(cells, v_dust, vf)
+            Kc, Kf = _rates(coag, cells, v_dust, vf, prec)
             r = coag.coag_step(rho, Kc, Kf, dt, h=h, mode=mode, prec=prec, rtol=rtol,
-                               atol_rel=atol_rel, max_sub=max_sub, nsub=nsubs[s], h_log=logs[s])
+                               atol_rel=atol_rel, max_sub=max_sub, nsub=nsubs[s], h_log=log,
+                               check_status=False)
             st = r["status"]
             if bool((st != 0).any()):
                 bad = int((st != 0).sum())
                 raise RuntimeError(f"coag_step: {bad} cells failed at call {s} "
                                    f"(status codes {sorted(set(st.tolist()))})")
+            width = max(1, int(nsubs[s].max()))
+            logs.append(log[:, :width].clone())
         ctx.coag, ctx.cells, ctx.v_dust, ctx.vf = coag, cells, v_dust, vf
         ctx.dt, ctx.n_steps, ctx.ckpt_every, ctx.prec = dt, n_steps, ckpt_every, prec
         ctx.logs, ctx.nsubs, ctx.ckpts = logs, nsubs, ckpts
@@ -71,13 +83,13 @@ class CoagStep(torch.autograd.Function):
             for s in range(s0, s1):
                 starts.append(rho.clone())
                 if s + 1 < s1:
-                    Kc, Kf = coag.coag_rates(cells, v_dust, vf)
+                    Kc, Kf = _rates(coag, cells, v_dust, vf, ctx.prec)
                     coag.coag_step(rho, Kc, Kf, ctx.dt, mode=L.REPLAY, prec=ctx.prec,
                                    nsub=ctx.nsubs[s], h_log=ctx.logs[s])
             for s in range(s1 - 1, s0 - 1, -1):
                 gi, ga, gv = coag.coag_step_backward(starts[s - s0], cells, v_dust, vf,
                                                      ctx.logs[s], ctx.nsubs[s], g,
-                                                     prec=L.PREC_FP64)
+                                                     prec=ctx.prec)
                 g = gi
                 g_alpha += ga
                 g_vfrag += gv

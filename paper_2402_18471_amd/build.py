@@ -8,7 +8,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcoag.so")
-SOURCES = ["coag_api.hip", "coag_kernels.hip", "coag_step2.hip", "coag_batch.hip"]
+SOURCES = ["coag_api.hip", "coag_kernels.hip", "coag_step2.hip", "coag_batch.hip",
+           "coag_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

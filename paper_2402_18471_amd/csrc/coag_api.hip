@@ -1,7 +1,7 @@
 // coag_api.hip -- the C ABI of libcoag (declared in include/coag.h): argument
 // validation on the host, context lifetime, workspaces and kernel launches.
 // Every numerical step of the path runs in the kernels of coag_kernels.hip,
-// coag_step2.hip and coag_batch.hip; this file only checks, allocates and
+// coag_step2.hip, coag_batch.hip and coag_adjoint.hip; this file only checks, allocates and
 // launches.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -28,6 +28,7 @@ struct coag_ctx {
     Tables T{};
     BatchTables B{};
     bool batch_fp64 = true;                // FP64 steps take the batched kernel when it applies
+    long adj_slab = 0;                     // cells per slab of the batched adjoint (0: by budget)
     // grow-only workspaces
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -186,6 +187,7 @@ int coag_create(const coag_grid *g, coag_ctx **out) {
     if (e == hipSuccess) e = build_batch_tables(T, b + o_batch, &ctx->B);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (const char *k = getenv("COAG_STEP_KERNEL")) ctx->batch_fp64 = strcmp(k, "cell") != 0;
+    if (const char *k = getenv("COAG_ADJ_SLAB_CELLS")) ctx->adj_slab = atol(k);
     if (e != hipSuccess) rc = fail(nullptr, COAG_EHIP, "coag_create: %s", hipGetErrorString(e));
     if (rc != COAG_OK) {
         (void)hipFree(ctx->block);
@@ -333,6 +335,51 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void 
     return COAG_OK;
 }
 
+// Workspace of the batched adjoint per slab of S cells (S a multiple of 16,
+// or all C cells): blocked rates (RT) and rate derivatives (GT), the forward
+// replay's step starts Ys and stage states Zs, the replay's state, slopes and
+// status, and v3.  (Zf, Xf: the rate-derivative factors Z, X.)
+struct AdjWs {
+    size_t Kc, Kf, Zf, Xf, Ys, Zs, y, slopes, status, v3, total;
+};
+
+static AdjWs adj_ws(int N, size_t P, long S, int L, int split, int gf32) {
+    const size_t Sb = ((size_t)S + kBatchCells - 1) / kBatchCells * kBatchCells;
+    const size_t rt = split ? 4 : 8, gt = gf32 ? 4 : 8;
+    AdjWs w;
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
+    w.Kc = take(rt * P * Sb);
+    w.Kf = take(rt * P * Sb);
+    w.Zf = take(gt * P * Sb);
+    w.Xf = take(gt * P * Sb);
+    w.Ys = take(8 * (size_t)N * (size_t)(L + 1) * (size_t)S);
+    w.Zs = take(8 * (size_t)N * 2 * (size_t)L * (size_t)S);
+    w.y = take(8 * (size_t)N * (size_t)S);
+    w.slopes = take(batch_ws_bytes(N, S, split, split ? COAG_RATES_BLK32 : COAG_RATES_BLK64));
+    w.status = take(4 * (size_t)S);
+    w.v3 = take(8 * (size_t)N * (size_t)S);
+    w.total = o;
+    return w;
+}
+
+// cells per slab: all of them if their workspace fits the budget, else as
+// many whole 16-cell batches as fit (at least 4096 cells, a launch that still
+// fills the GPU)
+constexpr size_t kAdjBudget = (size_t)8 << 30;
+
+static long adj_slab_cells(const coag_ctx *ctx, long C, int L, int split, int gf32) {
+    if (ctx->adj_slab > 0) {
+        const long s = (ctx->adj_slab + kBatchCells - 1) / kBatchCells * kBatchCells;
+        return s < C ? s : C;
+    }
+    if (adj_ws(ctx->N, ctx->P, C, L, split, gf32).total <= kAdjBudget) return C;
+    const size_t per16 = adj_ws(ctx->N, ctx->P, 16, L, split, gf32).total;
+    long s = (long)(kAdjBudget / per16) * kBatchCells;
+    if (s < 4096) s = 4096;
+    return s < C ? s : C;
+}
+
 int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coag_cells *cells,
                        const double *v_dust, const double *v_frag, const double *h_log,
                        int32_t log_stride, const int32_t *nsub, const double *g_out,
@@ -343,60 +390,94 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
         return fail(ctx, COAG_EINVAL, "coag_step_backward: bad C = %lld", (long long)C);
     if (prec != COAG_PREC_FP64 && prec != COAG_PREC_SPLIT_BF16)
         return fail(ctx, COAG_EINVAL, "coag_step_backward: unknown precision %d", prec);
-    if (prec == COAG_PREC_SPLIT_BF16)
-        return fail(ctx, COAG_ENOTSUP, "coag_step_backward: the adjoint runs in FP64 only");
     if (log_stride < 1) return fail(ctx, COAG_EINVAL, "coag_step_backward: log_stride must be >= 1");
+    const bool split = prec == COAG_PREC_SPLIT_BF16;
+    const bool batched = adj_batch_available(ctx->T, ctx->B) && (split || ctx->batch_fp64);
+    if (split && !batched)
+        return fail(ctx, COAG_ENOTSUP,
+                    "coag_step_backward: the split-BF16 adjoint needs the batched kernels "
+                    "(N >= 16 bins whose products of each row fit a 16-bin window, and the "
+                    "state of 16 cells within the LDS of one workgroup)");
     if (C == 0) return COAG_OK;
     if (int r = check_cells(ctx, cells)) return r;
     if (!rho_in || !v_dust || !v_frag || !h_log || !nsub || !g_out || !g_in || !g_alpha || !g_vfrag)
         return fail(ctx, COAG_EINVAL, "coag_step_backward: NULL array");
     if (int r = set_device(ctx)) return r;
     const size_t P = ctx->P, N = ctx->N;
-    // The forward replay that keeps the step-start and stage states runs on
-    // the batched step (REPLAY) where that applies, else inside k_adjoint.
-    // The batched replay works on a copy of rho_in, with its slopes and
-    // status after the adjoint's arrays, and reorders the [C][P] rates in the
-    // dJ/dK area, which k_adjoint clears before it accumulates there (so the
-    // rate arrays are sized for whole 16-cell batches).
-    const bool batched = ctx->batch_fp64 && batch_available(ctx->T, ctx->B);
-    const size_t Cb = ((size_t)C + kBatchCells - 1) / kBatchCells * kBatchCells;
-    const size_t bK = align256(8 * P * Cb);
+    const CellArrays ca = cell_arrays(cells);
+    hipStream_t st = (hipStream_t)stream;
+    if (batched) {
+        // per slab: rates and their derivatives (blocked), the forward replay
+        // keeping every step's start and stage states, then the reverse sweep
+        const int gf32 = split ? 1 : 0;
+        const int L = log_stride;
+        const long S = adj_slab_cells(ctx, C, L, split, gf32);
+        const AdjWs w = adj_ws(ctx->N, P, S, L, split, gf32);
+        if (int r = ensure_ws(ctx, w.total)) return r;
+        char *b = (char *)ctx->ws;
+        for (long s0 = 0; s0 < C; s0 += S) {
+            const long Cs = C - s0 < S ? C - s0 : S;
+            const CellArrays cs{ca.T + s0, ca.rho_g + s0, ca.c_s + s0, ca.Omega + s0,
+                                ca.H + s0, ca.nu_mol + s0, ca.alpha + s0};
+            const double *vd = v_dust + (size_t)s0 * N * 3, *vf = v_frag + s0;
+            HIP_TRY(ctx, launch_rates_blocked(ctx->T, Cs, cs, vd, vf, split ? 1 : 0, b + w.Kc,
+                                              b + w.Kf, st));
+            HIP_TRY(ctx, launch_rate_derivs_blocked(ctx->T, Cs, cs, vd, vf, gf32, b + w.Zf,
+                                                    b + w.Xf, st));
+            double *y = (double *)(b + w.y);
+            HIP_TRY(ctx, hipMemcpyAsync(y, rho_in + (size_t)s0 * N, 8 * N * (size_t)Cs,
+                                        hipMemcpyDeviceToDevice, st));
+            StepArgs sa;
+            sa.rho = y;
+            sa.Kc = (const double *)(b + w.Kc);
+            sa.Kf = (const double *)(b + w.Kf);
+            sa.dt = 0.0;
+            sa.h = nullptr;
+            sa.rtol = sa.atol_rel = sa.h_min_rel = 0.0;
+            sa.max_sub = L;
+            sa.mode = COAG_REPLAY;
+            sa.renorm = 0;
+            sa.nsub = const_cast<int32_t *>(nsub + s0);            // read only in REPLAY
+            sa.nrej = nullptr;
+            sa.status = (int32_t *)(b + w.status);
+            sa.h_log = const_cast<double *>(h_log + (size_t)s0 * L);  // read only in REPLAY
+            sa.Ys = (double *)(b + w.Ys);
+            sa.Zs = (double *)(b + w.Zs);
+            HIP_TRY(ctx, launch_step_batch(ctx->T, ctx->B, Cs, sa, split ? 1 : 0,
+                                           split ? COAG_RATES_BLK32 : COAG_RATES_BLK64,
+                                           (double *)(b + w.slopes), st));
+            AdjBatchArgs aa;
+            aa.Kc = b + w.Kc;
+            aa.Kf = b + w.Kf;
+            aa.Z = b + w.Zf;
+            aa.X = b + w.Xf;
+            aa.v_frag = vf;
+            aa.Ys = sa.Ys;
+            aa.Zs = sa.Zs;
+            aa.h_log = h_log + (size_t)s0 * L;
+            aa.L = L;
+            aa.nsub = nsub + s0;
+            aa.status = sa.status;
+            aa.g_out = g_out + (size_t)s0 * N;
+            aa.g_in = g_in + (size_t)s0 * N;
+            aa.v3 = (double *)(b + w.v3);
+            aa.g_alpha = g_alpha + s0;
+            aa.g_vfrag = g_vfrag + s0;
+            HIP_TRY(ctx, launch_adjoint_batch(ctx->T, ctx->B, Cs, aa, split ? 1 : 0, gf32, st));
+        }
+        return COAG_OK;
+    }
+    // one cell per workgroup (grids the batched kernels do not cover, or
+    // COAG_STEP_KERNEL=cell): rates [C][P], dJ/dK per pair, stage states
+    const size_t bK = align256(8 * P * (size_t)C);
     const size_t bY = align256(8 * N * (size_t)(log_stride + 1) * (size_t)C);
     const size_t bZ = align256(8 * N * 2 * (size_t)log_stride * (size_t)C);
-    const size_t bR = batched ? align256(8 * N * (size_t)C) : 0;
-    const size_t bW = batched ? align256(batch_ws_bytes(ctx->N, C, 0, COAG_RATES_BLK64)) : 0;
-    const size_t bS = batched ? align256(4 * (size_t)C) : 0;
-    if (int r = ensure_ws(ctx, 4 * bK + bY + bZ + bR + bW + bS)) return r;
+    if (int r = ensure_ws(ctx, 4 * bK + bY + bZ)) return r;
     char *w = (char *)ctx->ws;
     double *Kc = (double *)w, *Kf = (double *)(w + bK), *gKc = (double *)(w + 2 * bK),
            *gKf = (double *)(w + 3 * bK), *Ys = (double *)(w + 4 * bK);
     double *Zs = (double *)(w + 4 * bK + bY);
-    const CellArrays ca = cell_arrays(cells);
-    hipStream_t st = (hipStream_t)stream;
     HIP_TRY(ctx, launch_rates(ctx->T, C, ca, v_dust, v_frag, Kc, Kf, st));
-    if (batched) {
-        char *wb = w + 4 * bK + bY + bZ;
-        double *y = (double *)wb;
-        HIP_TRY(ctx, hipMemcpyAsync(y, rho_in, 8 * N * (size_t)C, hipMemcpyDeviceToDevice, st));
-        StepArgs sa;
-        sa.rho = y;
-        sa.Kc = Kc;
-        sa.Kf = Kf;
-        sa.dt = 0.0;
-        sa.h = nullptr;
-        sa.rtol = sa.atol_rel = sa.h_min_rel = 0.0;
-        sa.max_sub = log_stride;
-        sa.mode = COAG_REPLAY;
-        sa.renorm = 0;
-        sa.nsub = const_cast<int32_t *>(nsub);       // read only in REPLAY
-        sa.nrej = nullptr;
-        sa.status = (int32_t *)(wb + bR + bW);
-        sa.h_log = const_cast<double *>(h_log);      // read only in REPLAY
-        sa.Ys = Ys;
-        sa.Zs = Zs;
-        HIP_TRY(ctx, launch_step_batch(ctx->T, ctx->B, C, sa, 0, COAG_RATES_CP64,
-                                       (double *)(wb + bR), st, gKc));
-    }
     AdjArgs a;
     a.rho_in = rho_in;
     a.Kc = Kc;
@@ -405,7 +486,7 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
     a.gKf = gKf;
     a.Ys = Ys;
     a.Zs = Zs;
-    a.replayed = batched ? 1 : 0;
+    a.replayed = 0;
     a.h_log = h_log;
     a.log_stride = log_stride;
     a.nsub = nsub;

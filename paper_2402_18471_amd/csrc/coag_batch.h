@@ -19,6 +19,14 @@ namespace coag {
 //   b64: FP64 B operands of v_mfma_f64_16x16x4f64 in crow order, [NC][8][64]
 //   b16: three BF16 limbs of the same entries for v_mfma_f32_16x16x32_bf16, in
 //        crow_c order, [NC][3][64] x 16 bytes
+//   a64: the same entries as A operands of the adjoint's v_mfma_f64_16x16x4f64
+//        (pairs as rows, bins as the K dimension), crow_c order,
+//        [NC][2 kinds][4 bin quads][64]: lane l holds pair 16q + l % 16, bin
+//        wb[i] + 4 t + l / 16
+//   a16: three BF16 limbs of the adjoint's A operands of
+//        v_mfma_f32_16x16x32_bf16, crow_c order, [NC][2 kinds][3 limbs][32] x
+//        16 bytes: entry l holds pair 16q + l % 16, bins wb[i] + 8 (l / 16) + e,
+//        e = 0..7
 struct BatchTables {
     int NC;
     int ok;                      // every row fits its window (else the path is off)
@@ -27,6 +35,8 @@ struct BatchTables {
     const int *wb;               // [N]
     const double *b64;
     const uint4 *b16;
+    const double *a64;
+    const uint4 *a16;
 };
 
 constexpr int kBatchCells = 16;
@@ -46,6 +56,39 @@ size_t batch_ws_bytes(int N, long C, int prec, int layout);
 // only); hipErrorNotSupported for other combinations
 // ws: batch_ws_bytes(N, C, prec, layout) bytes, or, with wk given, the
 // slope part only and wk the [C][P] reordering area (FP64 [C][P] rates)
+// Reverse sweep of the batched adjoint (coag_adjoint.hip) over a frozen step
+// sequence, for C cells whose rates (blocked, RT = float or double) and
+// rate-derivative factors Z, X (blocked, GT; pair_rate_derivs) are given; Ys,
+// Zs hold the forward replay's step starts and stage states (layout of
+// AdjArgs, stride L = log_stride).
+struct AdjBatchArgs {
+    const void *Kc, *Kf;                 // [ceil(C/16)][P][16] RT
+    const void *Z, *X;                   // [ceil(C/16)][P][16] GT
+    const double *v_frag;                // [C]
+    const double *Ys, *Zs;
+    const double *h_log;
+    int L;
+    const int32_t *nsub;
+    const int32_t *status;               // replay status per cell (non-zero: outputs NaN)
+    const double *g_out;
+    double *g_in;                        // may equal g_out
+    double *v3;                          // workspace [C][N]
+    double *g_alpha, *g_vfrag;
+};
+
+// whether the batched adjoint runs for this context (the batched step does,
+// and its LDS fits)
+bool adj_batch_available(const Tables &T, const BatchTables &B);
+// the rate-derivative factors Z, X (pair_rate_derivs) in the 16-cell-blocked
+// layout, double (f32 = 0) or float (f32 = 1)
+hipError_t launch_rate_derivs_blocked(const Tables &T, long C, const CellArrays &cells,
+                                      const double *v_dust, const double *v_frag, int f32,
+                                      void *Z, void *X, hipStream_t st);
+// prec 0: FP64 rates and derivatives, FP64 matrix cores; prec 1: FP32 rates,
+// derivatives of type given by gf32, split-BF16 matrix products
+hipError_t launch_adjoint_batch(const Tables &T, const BatchTables &B, long C,
+                                const AdjBatchArgs &a, int prec, int gf32, hipStream_t st);
+
 hipError_t launch_step_batch(const Tables &T, const BatchTables &B, long C, const StepArgs &a,
                              int prec, int layout, double *ws, hipStream_t st,
                              void *wk = nullptr);

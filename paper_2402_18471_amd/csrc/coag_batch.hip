@@ -30,67 +30,13 @@
 #include <math.h>
 
 #include "coag_batch.h"
+#include "coag_batch_common.h"
 
 namespace coag {
 
 namespace {
 
-constexpr int kBC = kBatchCells;
-constexpr int kBWaves = 8;
-constexpr int kBBlock = 64 * kBWaves;
-constexpr int kWin = 16;
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-// round-to-nearest-even BF16 limbs of x: x = a0 + a1 + a2 + O(2^-25 |x|)
-struct Limbs {
-    __bf16 a0, a1, a2;
-};
-__device__ __forceinline__ Limbs split3(float x) {
-    Limbs L;
-    L.a0 = (__bf16)x;
-    const float r1 = x - (float)L.a0;
-    L.a1 = (__bf16)r1;
-    const float r2 = r1 - (float)L.a1;
-    L.a2 = (__bf16)r2;
-    return L;
-}
-
-// the same for eight values, as the BF16x8 operands of one MFMA, two values
-// per conversion instruction
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-struct Limbs8 {
-    bf16x8 a0, a1, a2;
-};
-__device__ __forceinline__ Limbs8 split3x8(const float (&x)[8]) {
-    union {
-        bf16x2 h[4];
-        bf16x8 v;
-    } A0, A1, A2;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const f32x2 v = {x[2 * e], x[2 * e + 1]};
-        A0.h[e] = __builtin_convertvector(v, bf16x2);
-        const f32x2 r1 = v - __builtin_convertvector(A0.h[e], f32x2);
-        A1.h[e] = __builtin_convertvector(r1, bf16x2);
-        const f32x2 r2 = r1 - __builtin_convertvector(A1.h[e], f32x2);
-        A2.h[e] = __builtin_convertvector(r2, bf16x2);
-    }
-    return Limbs8{A0.v, A1.v, A2.v};
-}
-
-// mass of the fragments of pair (i, j), total minus remnant (eq. `fragrem`),
-// evaluated exactly as the pair tables are: no contraction into an FMA
-__device__ __forceinline__ double frag_mass(double mi, double mj, double chi, bool &crater) {
-#pragma clang fp contract(off)
-    const double cm = chi * mj;
-    crater = cm < mi;
-    const double mrem = crater ? mi - cm : 0.0;
-    return (mi + mj) - mrem;
-}
+using namespace bc;
 
 // chunks of rates in flight per wave: the FP64 form has the registers for a
 // deeper ring (one 8-wave workgroup per CU either way)
@@ -184,6 +130,39 @@ __global__ void k_batch_b(Tables T, int NC, const int *crow, const int *crow_c, 
     b16[((long)ch * 3 + 2) * 64 + lane] = L2.u;
 }
 
+// one thread per (chunk, lane): the adjoint's A operands for the chunk
+// (column-block order), pair 16q + l % 16 as the row.  FP64: bin quad t, bin
+// wb + 4t + l / 16; BF16 (lanes 0..31): bins wb + 8 (l / 16) + e
+__global__ void k_adj_a(Tables T, int NC, const int *crow_c, const int *wb, double *a64,
+                        uint4 *a16) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)NC * 64) return;
+    const int ch = (int)(t >> 6), lane = (int)(t & 63);
+    const int i = crow_c[ch] & 0xffff, q = crow_c[ch] >> 16;
+    const int j = 16 * q + (lane & 15);
+    for (int kind = 0; kind < 2; ++kind)
+        for (int tq = 0; tq < 4; ++tq)
+            a64[(((long)ch * 2 + kind) * 4 + tq) * 64 + lane] =
+                d_entry(T, i, j, kind, wb[i] + 4 * tq + (lane >> 4));
+    if (lane >= 32) return;
+    for (int kind = 0; kind < 2; ++kind) {
+        union {
+            __bf16 h[8];
+            uint4 u;
+        } L0, L1, L2;
+        for (int e = 0; e < 8; ++e) {
+            const Limbs L = split3((float)d_entry(T, i, j, kind, wb[i] + 8 * (lane >> 4) + e));
+            L0.h[e] = L.a0;
+            L1.h[e] = L.a1;
+            L2.h[e] = L.a2;
+        }
+        uint4 *o = a16 + ((long)ch * 2 + kind) * 3 * 32 + lane;
+        o[0] = L0.u;
+        o[32] = L1.u;
+        o[64] = L2.u;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // per-cell control (one entry per cell of the batch, in LDS)
 // ---------------------------------------------------------------------------
@@ -191,37 +170,6 @@ struct Ctl {
     double h, t, hh, mass0, atol, nmax, inv_nmax, fac;
     int nacc, nrej, status, nfix, clipped, active, live, pad;
 };
-
-__device__ __forceinline__ double wave_sum_d(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max_d(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_min_d(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Row stride of the per-cell LDS arrays: odd, so that 16 cells' entries of
-// one bin fall in 16 different banks (a stride that is a multiple of 2^k
-// folds them onto 32 / 2^(k-1) banks: 8-way conflicts at N = 80, 4-way at 200)
-__host__ __device__ constexpr int batch_row_stride(int N) { return N | 1; }
-
-// The batch a workgroup takes.  Workgroups are dealt to the eight XCDs in
-// turn (workgroup w to XCD w mod 8), and each XCD runs its share from its own
-// queue, so with the plain mapping XCD x would take every batch b = x mod 8:
-// on a disc stored radius by radius with eight batches per radius, always the
-// same height above the midplane, and the XCD with the stiffest layer would
-// finish last.  Workgroup 8k + x takes batch 8k + (x + k) mod 8 instead (the
-// last, incomplete group of eight keeps the plain mapping): each XCD sees
-// every layer, and batches still start in about index order.
-__device__ __forceinline__ long batch_of(long w, long nb) {
-    const long k = w >> 3;
-    return 8 * k + 8 > nb ? w : 8 * k + ((w + k) & 7);
-}
 
 template <int PREC, typename RT, bool BLK>
 __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B, StepArgs a,
@@ -890,7 +838,8 @@ hipError_t allow_lds_b(K kernel, size_t bytes) {
 size_t batch_tables_bytes(int N) {
     const size_t NC = (size_t)n_chunks(N);
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return 2 * al(4 * NC) + al(4 * (size_t)N) + al(8 * NC * 8 * 64) + al(16 * NC * 3 * 64) + 256;
+    return 2 * al(4 * NC) + al(4 * (size_t)N) + al(8 * NC * 8 * 64) + al(16 * NC * 3 * 64) +
+           al(8 * NC * 2 * 4 * 64) + al(16 * NC * 2 * 3 * 32) + 256;
 }
 
 hipError_t build_batch_tables(const Tables &T, void *mem, BatchTables *B) {
@@ -908,6 +857,10 @@ hipError_t build_batch_tables(const Tables &T, void *mem, BatchTables *B) {
     p += al(8 * (size_t)NC * 8 * 64);
     uint4 *b16 = (uint4 *)p;
     p += al(16 * (size_t)NC * 3 * 64);
+    double *a64 = (double *)p;
+    p += al(8 * (size_t)NC * 2 * 4 * 64);
+    uint4 *a16 = (uint4 *)p;
+    p += al(16 * (size_t)NC * 2 * 3 * 32);
     int *bad = (int *)p;
     B->NC = NC;
     B->ok = 0;
@@ -916,6 +869,8 @@ hipError_t build_batch_tables(const Tables &T, void *mem, BatchTables *B) {
     B->wb = wb;
     B->b64 = b64;
     B->b16 = b16;
+    B->a64 = a64;
+    B->a16 = a16;
     if (N < kWin) return hipSuccess;                 // window wider than the grid: path off
     int *h = (int *)malloc(sizeof(int) * NC);
     if (!h) return hipErrorOutOfMemory;
@@ -933,6 +888,8 @@ hipError_t build_batch_tables(const Tables &T, void *mem, BatchTables *B) {
     hipLaunchKernelGGL(k_batch_rows, dim3((N + 63) / 64), dim3(64), 0, 0, T, wb, bad);
     hipLaunchKernelGGL(k_batch_b, dim3((unsigned)((NC * 64L + 255) / 256)), dim3(256), 0, 0, T, NC,
                        crow, crow_c, wb, b64, b16);
+    hipLaunchKernelGGL(k_adj_a, dim3((unsigned)((NC * 64L + 255) / 256)), dim3(256), 0, 0, T, NC,
+                       crow_c, wb, a64, a16);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int hb = 1;
     if ((e = hipMemcpy(&hb, bad, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) return e;

@@ -139,6 +139,53 @@ __device__ inline void pair_rates(const CellRate &r, const Grain &gi, const Grai
     kf = K * pf;
 }
 
+// What the adjoint needs of one pair's rate derivatives with respect to the
+// cell's alpha and v_frag (i >= j, so St_i >= St_j; plain FP64 divisions and
+// square root).  alpha enters through v_turb^2 = alpha c_s^2 V(delta, S) with
+// delta = Re^(-1/2) proportional to alpha^(-1/2) and S = clamp(y* St_i,
+// delta, 1), which moves with delta only while it sits on the lower clamp:
+//   d v_turb^2 / d alpha = c_s^2 (V - delta/2 dV/ddelta),
+// and Z = (d dv / d alpha) / dv = (d v_turb^2 / d alpha) / (2 dv^2).
+// v_frag enters through y = 1.5 (v_frag / dv)^2 in p_frag = (1 + y) e^-y.
+// With X = 2 y^2 / (1 + y), the derivatives follow from the rates themselves
+// (Kc = w K p_coag, Kf = w K p_frag, K = sigma dv):
+//   dKc/dalpha = Z (Kc - X Kf),   dKf/dalpha = Z (1 + X) Kf,
+//   dKf/dv_frag = -X Kf / v_frag = -dKc/dv_frag.
+// With alpha = 0 the turbulent term is off and Z = 0; with dv = 0, or where
+// e^-y is zero in FP64 (Kf = 0 there), X = 0.
+struct RateDerivs {
+    double Z, X;
+};
+
+__device__ inline RateDerivs pair_rate_derivs(const CellRate &r, double alpha, double cs2,
+                                              double st_i, double st_j, double im_i,
+                                              double im_j, double vlam2) {
+    double vturb2 = 0.0, dvt2_da = 0.0;
+    if (r.turb) {
+        const double d = r.delta;
+        double S = kYStar * st_i, dS = 0.0;
+        if (S < d) { S = d; dS = 1.0; }
+        if (S > 1.0) { S = 1.0; dS = 0.0; }
+        const double a1 = st_i * st_i, a2 = st_j * st_j, f12 = (st_i - st_j) / (st_i + st_j);
+        const double V = f12 * (a1 / (S + st_i) - a1 / (1.0 + st_i) - a2 / (S + st_j) +
+                                a2 / (1.0 + st_j)) +
+                         2.0 * (S - d) + a1 / (st_i + S) - a1 / (st_i + d) + a2 / (st_j + S) -
+                         a2 / (st_j + d);
+        const double Si2 = (S + st_i) * (S + st_i), Sj2 = (S + st_j) * (S + st_j);
+        const double dV_dS = f12 * (-a1 / Si2 + a2 / Sj2) + 2.0 - a1 / Si2 - a2 / Sj2;
+        const double dV_dd = -2.0 + a1 / ((st_i + d) * (st_i + d)) + a2 / ((st_j + d) * (st_j + d));
+        vturb2 = alpha * cs2 * V;
+        dvt2_da = cs2 * (V - 0.5 * d * (dV_dd + dV_dS * dS));
+    }
+    RateDerivs o{0.0, 0.0};
+    const double dv2 = r.kbt * (im_i + im_j) + vturb2 + vlam2;
+    if (!(dv2 > 0.0)) return o;
+    o.Z = dvt2_da / (2.0 * dv2);
+    const double y = 1.5 * r.vf * r.vf / dv2;
+    o.X = y < kExpZeroY ? 2.0 * y * y / (1.0 + y) : 0.0;
+    return o;
+}
+
 // Pair rates of one block of 16 cells (cells cell0 .. cell0 + 15) in the
 // 16-cell-blocked layout (rate of cell c, pair p at ((c / 16) P + p) 16 +
 // c % 16; cells past C get zeros), double or rounded to float, by NT threads

@@ -176,16 +176,20 @@ def test_split_rejections_and_host_errors(O):
     with pytest.raises(L.CoagError) as e:       # FP32 rates with the FP64 step
         ctx.coag_step(rho, Kc32, Kf32, d["dt"], prec=0)
     assert e.value.code == L.COAG_EINVAL
-    with pytest.raises(L.CoagError) as e:       # the adjoint is FP64 only
-        ctx.coag_step_backward(rho, cells, _t(d["v_dust"]), _t(d["v_frag"]),
-                               torch.zeros((4, 1), dtype=torch.float64, device=DEV),
-                               torch.zeros(4, dtype=torch.int32, device=DEV), rho, prec=1)
-    assert e.value.code == L.COAG_ENOTSUP
     m, me, s = coag_mass_grid(8, 1e-5, 1e-3)    # fewer bins than the 16-bin window
     small = coag_create(m, me, s)
     z = torch.zeros((1, 36), dtype=torch.float64, device=DEV)
     with pytest.raises(L.CoagError) as e:
         small.coag_step(torch.ones((1, 8), dtype=torch.float64, device=DEV), z, z, 1.0, prec=1)
+    assert e.value.code == L.COAG_ENOTSUP
+    c1 = {k: v[:1].contiguous() for k, v in cells.items()}
+    with pytest.raises(L.CoagError) as e:       # nor the split adjoint
+        small.coag_step_backward(torch.ones((1, 8), dtype=torch.float64, device=DEV), c1,
+                                 torch.zeros((1, 8, 3), dtype=torch.float64, device=DEV),
+                                 _t(d["v_frag"][:1]),
+                                 torch.zeros((1, 1), dtype=torch.float64, device=DEV),
+                                 torch.zeros(1, dtype=torch.int32, device=DEV),
+                                 torch.ones((1, 8), dtype=torch.float64, device=DEV), prec=1)
     assert e.value.code == L.COAG_ENOTSUP
     torch.cuda.synchronize()
     assert torch.equal(rho, before)
