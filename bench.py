@@ -110,12 +110,50 @@ def parse():
     return ap.parse_args()
 
 
+ADJ_BUDGET = 8 << 30        # the library's workspace budget for one adjoint slab
+
+
+def evolve_memory_plan(C, N, calls, ckpt, width, prec_split):
+    """Device bytes the differentiable run holds at its peak (the backward
+    pass), on the host from the shapes: the rates of one call (16-cell-blocked
+    FP32 for split; FP64 [C][P] plus the step's reordered copy for FP64), the
+    step's slope workspace, the adjoint's slab workspace (the library's rule:
+    rates, their derivative factors, step starts and stage states of `width`
+    steps, replay state, slopes and v3 for as many whole 16-cell batches as
+    fit ADJ_BUDGET, all cells if they fit), checkpoints every ckpt calls, the
+    compacted step logs (width per call, an upper bound) and step counts,
+    one segment's start states, and the state, its gradient and g_out."""
+    P = N * (N + 1) // 2
+    Cb = -(-C // 16) * 16
+    al = lambda b: -(-b // 256) * 256
+    rates = 2 * Cb * P * 4 if prec_split else 2 * C * P * 8 + Cb * P * 2 * 8
+    slopes = al(Cb * 5 * N * 8)
+
+    def adj(S):
+        Sb = -(-S // 16) * 16
+        rt, gt = (4, 4) if prec_split else (8, 8)
+        return (2 * al(rt * P * Sb) + 2 * al(gt * P * Sb) + al(8 * N * (width + 1) * S) +
+                al(8 * N * 2 * width * S) + al(8 * N * S) + al(Sb * 5 * N * 8) + al(4 * S) +
+                al(8 * N * S))
+    S = C if adj(C) <= ADJ_BUDGET else max(4096, ADJ_BUDGET // adj(16) * 16)
+    S = min(S, C)
+    state = C * N * 8
+    plan = {"rates_one_call": rates, "step_workspace": slopes, "adjoint_slab_cells": S,
+            "adjoint_workspace": adj(S), "checkpoints": -(-calls // ckpt) * state,
+            "step_logs_upper_bound": calls * C * width * 8, "step_counts": calls * C * 4,
+            "segment_starts": ckpt * state, "state_grads": 4 * state}
+    plan["total"] = sum(v for k, v in plan.items() if k != "adjoint_slab_cells")
+    return {k: (v / 1e9 if k != "adjoint_slab_cells" else v) for k, v in plan.items()}
+
+
 def evolve(args):
     """Forward and backward time of n differentiable coagulation calls
     (paper_2402_18471_amd.autograd.coag_evolve: ADAPTIVE, checkpoint every
-    ckpt calls; the backward recomputes each segment and runs the FP64
-    adjoint) on one disc, loss = sum over cells of the mass-weighted mean
-    ln s, and the device memory in use at the end of each pass."""
+    ckpt calls; the backward recomputes each segment and runs the adjoint in
+    the forward's precision) on one disc, loss = sum over cells of the
+    mass-weighted mean ln s; the device memory in use, sampled after every
+    checkpoint segment of both passes, beside the plan computed from the
+    shapes."""
     import torch
     from paper_2402_18471_amd import disc
     from paper_2402_18471_amd import _lib as L
@@ -132,18 +170,35 @@ def evolve(args):
     al = t(d["cells"]["alpha"]).requires_grad_(True)
     vf = t(d["v_frag"]).requires_grad_(True)
     lns = t(np.log(s))
-    prec = L.PREC_SPLIT_BF16 if args.evolve_prec == "split" else L.PREC_FP64
+    split = args.evolve_prec == "split"
+    prec = L.PREC_SPLIT_BF16 if split else L.PREC_FP64
+    max_sub = 64
+    plan = evolve_memory_plan(cfg.n_cells, cfg.n_bins, args.evolve_calls, args.evolve_ckpt,
+                              max_sub, split)
+    progress(f"evolve {cfg.name}: {args.evolve_calls} calls, {args.evolve_prec}; planned peak "
+             f"<= {plan['total']:.1f} GB (step logs at their {max_sub}-step upper bound)")
     free0, total = torch.cuda.mem_get_info()
-    progress(f"evolve {cfg.name}: {args.evolve_calls} calls, {args.evolve_prec} forward")
+    peak = {"forward": 0.0, "backward": 0.0}
+    tick = {"t": time.perf_counter()}
+
+    def on_segment(phase, done, n):
+        torch.cuda.synchronize()
+        used = (total - torch.cuda.mem_get_info()[0]) / 1e9
+        peak[phase] = max(peak[phase], used)
+        now = time.perf_counter()
+        progress(f"{phase}: {done}/{n} calls, {now - tick['t']:.1f} s, device memory {used:.1f} GB")
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = coag_evolve(ctx, rho0, al, vf, cells, t(d["v_dust"]), float(d["dt"]), args.evolve_calls,
-                      ckpt_every=args.evolve_ckpt, prec=prec, max_sub=64)
+                      ckpt_every=args.evolve_ckpt, prec=prec, max_sub=max_sub,
+                      progress=on_segment)
     J = ((out * lns).sum(1) / out.sum(1)).sum()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     used_fwd = (total - torch.cuda.mem_get_info()[0]) / 1e9
     progress(f"forward {t1 - t0:.2f} s")
+    tick["t"] = t1
     J.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -153,10 +208,14 @@ def evolve(args):
     print(json.dumps({
         "workload": cfg.name, "cells": cfg.n_cells, "bins": cfg.n_bins, "calls": args.evolve_calls,
         "ckpt_every": args.evolve_ckpt, "forward_precision": args.evolve_prec,
-        "adjoint_precision": "fp64", "forward_s": t1 - t0, "backward_s": t2 - t1,
+        "adjoint_precision": args.evolve_prec, "forward_s": t1 - t0, "backward_s": t2 - t1,
         "backward_over_forward": (t2 - t1) / (t1 - t0),
+        "cell_calls_per_s_forward": cfg.n_cells * args.evolve_calls / (t1 - t0),
         "device_memory_in_use_gb": {"before": (total - free0) / 1e9, "after_forward": used_fwd,
-                                    "after_backward": used_bwd},
+                                    "after_backward": used_bwd,
+                                    "max_sampled_forward": peak["forward"],
+                                    "max_sampled_backward": peak["backward"]},
+        "memory_plan_gb": plan,
         "gradients_finite": bool(all(torch.isfinite(x).all() for x in g)),
         "data": "synthetic disc, forward = coag_rates + ADAPTIVE coag_step per call"}), flush=True)
 
