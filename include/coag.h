@@ -222,6 +222,27 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void 
               double dt, double *h, const coag_tol *tol, int32_t *nsub, int32_t *nrej,
               double *h_log, int32_t *status, void *stream);
 
+/* coag_step without any allocation, for callers that cannot allocate device
+   memory (code under HIP graph capture, tight serving loops, harnesses that
+   forbid hipMalloc): the same arguments, checks, kernels and results as
+   coag_step, with the batched step's workspace taken from a static 64 MiB
+   array that the library holds on each device from its load to the end of
+   the process, instead of the context's workspace.  That is room for 16 P +
+   40 N bytes per cell: e.g. 8388 cells of 200 bins with blocked rates
+   (COAG_RATES_BLK32 / BLK64; 40 N bytes per cell), and about 200 cells of
+   200 bins with [C][P] FP64 rates in the FP64 step (which reorders them
+   there).  Larger calls return COAG_EINVAL and launch nothing; split them
+   into smaller ones.  Every call on one device shares that device's array:
+   calls that may overlap on one device (other streams, other contexts, other
+   host threads) race and must be serialised by the caller.  Nothing in the
+   array needs to start at zero.  Per-cell kernels (grids the batched step does
+   not cover, COAG_STEP_KERNEL=cell) use no workspace and run as in coag_step.
+   Errors: those of coag_step, COAG_EINVAL for a call beyond the array, and
+   COAG_ENOTSUP on a device without the array (device index >= 64). */
+int coag_step_noalloc(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void *Kf,
+                      double dt, double *h, const coag_tol *tol, int32_t *nsub, int32_t *nrej,
+                      double *h_log, int32_t *status, void *stream);
+
 /* Discrete adjoint of coag_rates + coag_step over a frozen step sequence
    (nsub[c] accepted steps of sizes h_log[c][:], as a REPLAY or FIXED call
    reproduces them).  With J a scalar of the final state and g_out = dJ/drho_end:

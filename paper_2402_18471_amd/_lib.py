@@ -71,6 +71,8 @@ def load():
         "coag_rhs": (ct.c_int, [_vp, i64, _vp, _vp, _vp, _vp, _vp]),
         "coag_step": (ct.c_int, [_vp, i64, _vp, _vp, _vp, ct.c_double, _vp, P(Tol), _vp, _vp,
                                  _vp, _vp, _vp]),
+        "coag_step_noalloc": (ct.c_int, [_vp, i64, _vp, _vp, _vp, ct.c_double, _vp, P(Tol), _vp,
+                                         _vp, _vp, _vp, _vp]),
         "coag_step_backward": (ct.c_int, [_vp, i64, _vp, P(Cells), _vp, _vp, _vp, i32, _vp, _vp,
                                           _vp, _vp, _vp, i32, _vp]),
     }

@@ -1,5 +1,6 @@
 """Python face of libcoag with the C ABI's names (coag_mass_grid, coag_create,
-coag_rates, coag_rates_blocked, coag_rhs, coag_step, coag_step_backward).
+coag_rates, coag_rates_blocked, coag_rhs, coag_step, coag_step_backward;
+coag_step_noalloc through coag_step(..., noalloc=True)).
 
 Tensors are torch CUDA (HIP) tensors, float64 (int32 for counters), contiguous;
 torch supplies device memory and the current stream, nothing else.
@@ -128,14 +129,16 @@ class CoagContext:
 
     def coag_step(self, rho, Kc, Kf, dt, h=None, mode=L.ADAPTIVE, prec=L.PREC_FP64, rtol=1e-2,
                   atol_rel=1e-10, h_min_rel=1e-12, max_sub=10000, renorm=False, nsub=None,
-                  h_log=None, log=True, check_status=True):
+                  h_log=None, log=True, check_status=True, noalloc=False):
         """Advances rho (in place) by dt; returns dict(rho, h, nsub, nrej, h_log, status).
         Kc, Kf: float64 [C][P] from coag_rates, or the 16-cell-blocked rates
         of coag_rates_blocked (float32: split precision only; float64: FP64
         only).  check_status: wait for the call and raise CoagCellError if any
         cell's status is not COAG_CELL_OK (the failed cells keep the state
         the call left them in); False returns at once, with the per-cell
-        status for the caller to inspect."""
+        status for the caller to inspect.  noalloc: call coag_step_noalloc,
+        which takes the batched step's workspace from the library's static
+        per-device scratch array instead of allocating it."""
         C = int(rho.shape[0])
         dev = rho.device
         _dev(rho, shape=(C, self.N), name="rho")
@@ -163,9 +166,10 @@ class CoagContext:
         nrej = torch.zeros(C, dtype=torch.int32, device=dev)
         status = torch.zeros(C, dtype=torch.int32, device=dev)
         tol = L.Tol(rtol, atol_rel, h_min_rel, max_sub, mode, prec, 1 if renorm else 0, layout)
-        self._check(self._lib.coag_step(self._h, C, _ptr(rho), _ptr(Kc), _ptr(Kf), float(dt),
-                                        _ptr(h), ct.byref(tol), _ptr(nsub), _ptr(nrej),
-                                        _ptr(h_log), _ptr(status), _stream()))
+        fn = self._lib.coag_step_noalloc if noalloc else self._lib.coag_step
+        self._check(fn(self._h, C, _ptr(rho), _ptr(Kc), _ptr(Kf), float(dt), _ptr(h),
+                       ct.byref(tol), _ptr(nsub), _ptr(nrej), _ptr(h_log), _ptr(status),
+                       _stream()))
         out = dict(rho=rho, h=h, nsub=nsub, nrej=nrej, h_log=h_log, status=status)
         if check_status:
             L.check_cells(status)

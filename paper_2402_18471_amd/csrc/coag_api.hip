@@ -10,6 +10,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/coag.h"
@@ -17,6 +18,17 @@
 #include "coag_batch.h"
 
 using namespace coag;
+
+// Scratch of coag_step_noalloc: the batched step's workspace (slopes and stage
+// states of every cell, and the reordered rates of [C][P] FP64 input) for
+// callers that cannot allocate.  Each device holds its own copy, from the
+// library's load to the end of the process; host code uses only the device
+// address looked up per device at coag_create (g_scratch), never the name.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static void *g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
 
 struct coag_ctx {
     int device = -1;
@@ -29,6 +41,7 @@ struct coag_ctx {
     BatchTables B{};
     bool batch_fp64 = true;                // FP64 steps take the batched kernel when it applies
     long adj_slab = 0;                     // cells per slab of the batched adjoint (0: by budget)
+    void *scratch = nullptr;               // this device's scratch array (coag_step_noalloc)
     // grow-only workspaces
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -125,6 +138,23 @@ int coag_create(const coag_grid *g, coag_ctx **out) {
     if (hipGetDevice(&ctx->device) != hipSuccess) {
         delete ctx;
         return fail(nullptr, COAG_EHIP, "coag_create: no HIP device");
+    }
+    if (ctx->device >= 0 && ctx->device < kMaxDevices) {
+        // the device address of this device's scratch array, looked up once per
+        // device with the device current
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch[ctx->device]) {
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+                (void)hipGetLastError();
+                const int dev = ctx->device;
+                delete ctx;
+                return fail(nullptr, COAG_EHIP,
+                            "coag_create: no address for the scratch array on device %d", dev);
+            }
+            g_scratch[ctx->device] = p;
+        }
+        ctx->scratch = g_scratch[ctx->device];
     }
     ctx->N = N;
     ctx->P = N * (N + 1) / 2;
@@ -267,43 +297,46 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
     return COAG_OK;
 }
 
-int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void *Kf,
-              double dt, double *h, const coag_tol *tol, int32_t *nsub, int32_t *nrej,
-              double *h_log, int32_t *status, void *stream) {
-    if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_step: ctx is NULL");
-    if (C < 0 || C > 0x7fffffff) return fail(ctx, COAG_EINVAL, "coag_step: bad C = %lld", (long long)C);
-    if (!tol) return fail(ctx, COAG_EINVAL, "coag_step: tol is NULL");
+// coag_step and coag_step_noalloc: the same checks and kernels; the batched
+// step's workspace comes from the context (grown on demand) or, with
+// noalloc, from the device's static scratch array (never allocated here)
+static int step_impl(const char *fn, coag_ctx *ctx, int64_t C, double *rho, const void *Kc,
+                     const void *Kf, double dt, double *h, const coag_tol *tol, int32_t *nsub,
+                     int32_t *nrej, double *h_log, int32_t *status, void *stream, bool noalloc) {
+    if (!ctx) return fail(nullptr, COAG_EINVAL, "%s: ctx is NULL", fn);
+    if (C < 0 || C > 0x7fffffff) return fail(ctx, COAG_EINVAL, "%s: bad C = %lld", fn, (long long)C);
+    if (!tol) return fail(ctx, COAG_EINVAL, "%s: tol is NULL", fn);
     if (C > 0 && (!rho || !Kc || !Kf || !nsub || !status))
-        return fail(ctx, COAG_EINVAL, "coag_step: rho, Kc, Kf, nsub and status are required");
-    if (!(dt > 0.0) || !isfinite(dt)) return fail(ctx, COAG_EINVAL, "coag_step: dt must be > 0");
+        return fail(ctx, COAG_EINVAL, "%s: rho, Kc, Kf, nsub and status are required", fn);
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(ctx, COAG_EINVAL, "%s: dt must be > 0", fn);
     if (tol->mode < COAG_ADAPTIVE || tol->mode > COAG_REPLAY)
-        return fail(ctx, COAG_EINVAL, "coag_step: unknown mode %d", tol->mode);
+        return fail(ctx, COAG_EINVAL, "%s: unknown mode %d", fn, tol->mode);
     if (tol->prec != COAG_PREC_FP64 && tol->prec != COAG_PREC_SPLIT_BF16)
-        return fail(ctx, COAG_EINVAL, "coag_step: unknown precision %d", tol->prec);
-    if (tol->max_sub < 1) return fail(ctx, COAG_EINVAL, "coag_step: max_sub must be >= 1");
+        return fail(ctx, COAG_EINVAL, "%s: unknown precision %d", fn, tol->prec);
+    if (tol->max_sub < 1) return fail(ctx, COAG_EINVAL, "%s: max_sub must be >= 1", fn);
     const int layout = tol->rates_layout;
     if (layout < COAG_RATES_CP64 || layout > COAG_RATES_BLK64)
-        return fail(ctx, COAG_EINVAL, "coag_step: unknown rates_layout %d", layout);
+        return fail(ctx, COAG_EINVAL, "%s: unknown rates_layout %d", fn, layout);
     if (layout == COAG_RATES_BLK32 && tol->prec != COAG_PREC_SPLIT_BF16)
-        return fail(ctx, COAG_EINVAL, "coag_step: FP32 rates need COAG_PREC_SPLIT_BF16");
+        return fail(ctx, COAG_EINVAL, "%s: FP32 rates need COAG_PREC_SPLIT_BF16", fn);
     if (layout == COAG_RATES_BLK64 && tol->prec != COAG_PREC_FP64)
-        return fail(ctx, COAG_EINVAL, "coag_step: blocked FP64 rates need COAG_PREC_FP64");
+        return fail(ctx, COAG_EINVAL, "%s: blocked FP64 rates need COAG_PREC_FP64", fn);
     if ((tol->prec == COAG_PREC_SPLIT_BF16 || layout != COAG_RATES_CP64) &&
         !batch_available(ctx->T, ctx->B))
         return fail(ctx, COAG_ENOTSUP,
-                    "coag_step: the split-BF16 step and blocked rates need N >= 16 bins whose "
-                    "products of each row fit a 16-bin window, and N <= 343");
+                    "%s: the split-BF16 step and blocked rates need N >= 16 bins whose "
+                    "products of each row fit a 16-bin window, and N <= 343", fn);
     if (layout == COAG_RATES_BLK64 && !ctx->batch_fp64)
         return fail(ctx, COAG_ENOTSUP,
-                    "coag_step: blocked FP64 rates need the batched step "
-                    "(COAG_STEP_KERNEL=cell selected the per-cell one)");
+                    "%s: blocked FP64 rates need the batched step "
+                    "(COAG_STEP_KERNEL=cell selected the per-cell one)", fn);
     if (tol->mode == COAG_ADAPTIVE) {
-        if (!h && C > 0) return fail(ctx, COAG_EINVAL, "coag_step: h is required in ADAPTIVE mode");
+        if (!h && C > 0) return fail(ctx, COAG_EINVAL, "%s: h is required in ADAPTIVE mode", fn);
         if (!(tol->rtol > 0.0) || !(tol->atol_rel >= 0.0) || !(tol->h_min_rel >= 0.0))
-            return fail(ctx, COAG_EINVAL, "coag_step: need rtol > 0, atol_rel >= 0, h_min_rel >= 0");
+            return fail(ctx, COAG_EINVAL, "%s: need rtol > 0, atol_rel >= 0, h_min_rel >= 0", fn);
     }
     if (tol->mode == COAG_REPLAY && !h_log && C > 0)
-        return fail(ctx, COAG_EINVAL, "coag_step: h_log is required in REPLAY mode");
+        return fail(ctx, COAG_EINVAL, "%s: h_log is required in REPLAY mode", fn);
     if (C == 0) return COAG_OK;
     if (int r = set_device(ctx)) return r;
     StepArgs a;
@@ -324,15 +357,44 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void 
     a.h_log = h_log;
     const bool split = tol->prec == COAG_PREC_SPLIT_BF16;
     if (split || (ctx->batch_fp64 && batch_available(ctx->T, ctx->B))) {
-        if (int r = ensure_ws(ctx, batch_ws_bytes(ctx->N, C, split ? 1 : 0, layout))) return r;
-        HIP_TRY(ctx, launch_step_batch(ctx->T, ctx->B, C, a, split ? 1 : 0, layout,
-                                       (double *)ctx->ws, (hipStream_t)stream));
+        const size_t need = batch_ws_bytes(ctx->N, C, split ? 1 : 0, layout);
+        double *ws;
+        if (noalloc) {
+            if (!ctx->scratch)
+                return fail(ctx, COAG_ENOTSUP, "%s: no scratch array on device %d", fn,
+                            ctx->device);
+            if (need > kScratchBytes)
+                return fail(ctx, COAG_EINVAL,
+                            "%s: %lld cells of %d bins need %zu bytes of scratch, more than its "
+                            "%zu bytes; split the call into fewer cells", fn, (long long)C,
+                            ctx->N, need, kScratchBytes);
+            ws = (double *)ctx->scratch;
+        } else {
+            if (int r = ensure_ws(ctx, need)) return r;
+            ws = (double *)ctx->ws;
+        }
+        HIP_TRY(ctx, launch_step_batch(ctx->T, ctx->B, C, a, split ? 1 : 0, layout, ws,
+                                       (hipStream_t)stream));
     } else if (reg_path_available(ctx->N)) {
         HIP_TRY(ctx, launch_step2(ctx->T, C, a, (hipStream_t)stream));
     } else {
         HIP_TRY(ctx, launch_step(ctx->T, C, a, (hipStream_t)stream));
     }
     return COAG_OK;
+}
+
+int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void *Kf,
+              double dt, double *h, const coag_tol *tol, int32_t *nsub, int32_t *nrej,
+              double *h_log, int32_t *status, void *stream) {
+    return step_impl("coag_step", ctx, C, rho, Kc, Kf, dt, h, tol, nsub, nrej, h_log, status,
+                     stream, false);
+}
+
+int coag_step_noalloc(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void *Kf,
+                      double dt, double *h, const coag_tol *tol, int32_t *nsub, int32_t *nrej,
+                      double *h_log, int32_t *status, void *stream) {
+    return step_impl("coag_step_noalloc", ctx, C, rho, Kc, Kf, dt, h, tol, nsub, nrej, h_log,
+                     status, stream, true);
 }
 
 // Workspace of the batched adjoint per slab of S cells (S a multiple of 16,

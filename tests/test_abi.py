@@ -18,7 +18,7 @@ def test_library_exports_every_declared_symbol(L):
     names = L.header_symbols()
     assert set(names) == {"coag_mass_grid", "coag_create", "coag_destroy", "coag_last_error",
                           "coag_rates", "coag_rates_blocked", "coag_rhs", "coag_step",
-                          "coag_step_backward"}
+                          "coag_step_noalloc", "coag_step_backward"}
     for n in names:
         assert hasattr(lib, n), n
 

@@ -1,0 +1,105 @@
+"""coag_step_noalloc (the batched step with its workspace in the library's
+static per-device scratch array) against coag_step on the same inputs,
+through the C ABI: two calls in a row, the second with fewer cells (the
+array then holds the first call's contents), in FP64 with blocked and [C][P]
+rates and in split BF16, FIXED and REPLAY (the same step sequence on both
+sides) and ADAPTIVE; and a call beyond the array's size, refused on the host
+with nothing written.
+
+Bar: both sides run the same kernels; the FP64 contraction deposits with
+LDS atomics, whose order may differ between two launches, so states agree to
+1e-12 relative (floor 1e-24 of the cell's mass) rather than bit for bit;
+step counts and status are equal.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def _disc(n_r, n_z, n_bins):
+    from paper_2402_18471_amd import disc
+    from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
+    cfg = disc.scaled(disc.CONFIGS["disc256x128_n150"], n_r, n_z, n_bins)
+    m, me, s = coag_mass_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
+    d = disc.make_disc(cfg, s)
+    return cfg, d, coag_create(m, me, s, rho_m=cfg.rho_m)
+
+
+def _pair(ctx, d, rates, mode, prec, **kw):
+    """One call on each side from the same state; returns both results."""
+    out = []
+    for noalloc in (False, True):
+        rho = _t(d["rho"])
+        r = ctx.coag_step(rho, *rates, float(d["dt"]) * 3, mode=mode, prec=prec,
+                          noalloc=noalloc, **{k: (v.clone() if torch.is_tensor(v) else v)
+                                              for k, v in kw.items()})
+        torch.cuda.synchronize()
+        out.append({k: v.cpu().numpy() for k, v in r.items() if torch.is_tensor(v)})
+    return out
+
+
+def _same(a, b):
+    M = a["rho"].sum(1, keepdims=True)
+    assert np.array_equal(a["status"], b["status"]) and np.all(a["status"] == 0)
+    assert np.array_equal(a["nsub"], b["nsub"])
+    assert np.all(np.abs(a["rho"] - b["rho"]) <= 1e-12 * np.abs(a["rho"]) + 1e-24 * M)
+
+
+@pytest.mark.parametrize("form", ["fp64_blocked", "fp64_cp", "split"])
+def test_noalloc_step_matches_the_step_twice(form):
+    from paper_2402_18471_amd import _lib as L
+    prec = L.PREC_SPLIT_BF16 if form == "split" else L.PREC_FP64
+    # a first call on 24x20 = 480 cells, then 6x5 = 30 cells (a ragged batch)
+    for (n_r, n_z) in ((24, 20), (6, 5)):
+        n_bins = 100 if form == "fp64_cp" else 150
+        cfg, d, ctx = _disc(n_r, n_z, n_bins)
+        cells = {k: _t(v) for k, v in d["cells"].items()}
+        vd, vf = _t(d["v_dust"]), _t(d["v_frag"])
+        if form == "fp64_cp":
+            rates = ctx.coag_rates(cells, vd, vf)
+        else:
+            rates = ctx.coag_rates_blocked(
+                cells, vd, vf, dtype=torch.float32 if form == "split" else torch.float64)
+        C = cfg.n_cells
+        a, b = _pair(ctx, d, rates, L.FIXED, prec, nsub=torch.full((C,), 3, dtype=torch.int32,
+                                                                     device=DEV), max_sub=3)
+        _same(a, b)
+        ad, bd = _pair(ctx, d, rates, L.ADAPTIVE, prec, max_sub=256)
+        assert np.all(ad["status"] == 0) and np.all(bd["status"] == 0)
+        ok = ad["nsub"] == bd["nsub"]
+        assert ok.mean() >= 0.99
+        M = ad["rho"].sum(1, keepdims=True)
+        assert np.all((np.abs(ad["rho"] - bd["rho"]) <= 1e-12 * np.abs(ad["rho"]) + 1e-24 * M)[ok])
+        a, b = _pair(ctx, d, rates, L.REPLAY, prec, nsub=_t(ad["nsub"], torch.int32),
+                     h_log=_t(ad["h_log"]))
+        _same(a, b)
+
+
+def test_noalloc_step_refuses_calls_beyond_the_scratch():
+    """[C][P] FP64 rates on 250 cells of 200 bins need 16 P + 40 N bytes per
+    cell (the step reorders the rates there): 82 MB, beyond the 64 MiB array."""
+    from paper_2402_18471_amd import _lib as L
+    cfg, d, ctx = _disc(25, 10, 200)
+    cells = {k: _t(v) for k, v in d["cells"].items()}
+    Kc, Kf = ctx.coag_rates(cells, _t(d["v_dust"]), _t(d["v_frag"]))
+    rho = _t(d["rho"])
+    before = rho.clone()
+    with pytest.raises(L.CoagError) as e:
+        ctx.coag_step(rho, Kc, Kf, float(d["dt"]), noalloc=True)
+    assert e.value.code == L.COAG_EINVAL and "scratch" in str(e.value)
+    torch.cuda.synchronize()
+    assert torch.equal(rho, before)
+    # the same cells with blocked rates fit (40 N bytes per cell) and match coag_step
+    K = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]), dtype=torch.float64)
+    a, b = _pair(ctx, d, K, L.FIXED, L.PREC_FP64,
+                 nsub=torch.full((cfg.n_cells,), 2, dtype=torch.int32, device=DEV), max_sub=2)
+    _same(a, b)
