@@ -11,8 +11,8 @@ evaluations, error estimate and FP64 update).
 Measured on the 256x128-cell, 150-bin disc:
   value          FP64 path (FP64 rates, batched FP64 matrix-core step)
   split_bf16     split-BF16 step with FP32 rates: throughput, speedup over the
-                 FP64 path, and its per-bin error against the FP64 GPU path
-                 (replaying the same steps) on a stratified sample of cells
+                 FP64 path, and its per-bin error against the FP64 oracle
+                 (replaying the split call's steps) on a stratified sample of cells
   adjoint        coag_step_backward time over forward (rates + step) time on
                  the 64x32-cell, 100-bin disc, FP64 and split BF16
   roofline       the FP64 step kernel against HBM bandwidth: algorithmic
@@ -262,30 +262,55 @@ def summarize_counters(fetch_csv, write_csv, bench_log):
     print(json.dumps(out))
 
 
-def cpu_baseline(cfg, disc_mod, n_cells, target_s=10.0, max_calls=2000):
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(cfg, disc_mod, n_cells, target_s=10.0, max_calls=2000, one_thread_s=5.0):
     """The oracle, untouched, on a bounded sample of the same workload:
     n_cells cells spread evenly over the disc, repeated coagulation calls
     (rates + adaptive step over dt, state carried) until about target_s of
-    CPU time has been spent."""
+    CPU time has been spent, on all the host's threads; then the same sample
+    from its start again on one thread for about one_thread_s."""
     import oracle as O
     g = O.make_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
     d = disc_mod.make_disc(cfg, g.s)
     idx = np.linspace(0, cfg.n_cells - 1, n_cells).astype(np.int64)
     sub = disc_mod.subset_cells(d, idx)
-    rho = sub["rho"].copy()
-    h = np.zeros(len(idx))
-    acc = calls = 0
-    t0 = time.perf_counter()
-    while calls < max_calls and time.perf_counter() - t0 < target_s:
-        Kc, Kf = O.rates(g, sub["cells"], sub["v_dust"], sub["v_frag"])
-        r = O.step(g, rho, Kc, Kf, sub["dt"], h=h)
-        rho, h = r["rho"], r["h"]
-        acc += int(r["nsub"].sum())
-        calls += 1
-    dt = time.perf_counter() - t0
-    return {"value": acc / dt, "unit": "cell-steps/s", "cores": O.num_threads(), "kind": "oracle",
+
+    def run(budget):
+        rho = sub["rho"].copy()
+        h = np.zeros(len(idx))
+        acc = calls = 0
+        t0 = time.perf_counter()
+        while calls < max_calls and time.perf_counter() - t0 < budget:
+            Kc, Kf = O.rates(g, sub["cells"], sub["v_dust"], sub["v_frag"])
+            r = O.step(g, rho, Kc, Kf, sub["dt"], h=h)
+            rho, h = r["rho"], r["h"]
+            acc += int(r["nsub"].sum())
+            calls += 1
+        return acc, calls, time.perf_counter() - t0
+
+    cores = O.num_threads()
+    acc, calls, dt = run(target_s)
+    O.set_num_threads(1)
+    try:
+        acc1, calls1, dt1 = run(one_thread_s)
+    finally:
+        O.set_num_threads(cores)
+    return {"value": acc / dt, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "one_thread_value": acc1 / dt1,
             "sample": f"{len(idx)} cells spread over the {cfg.n_cells}-cell disc, {calls} coagulation "
-                      f"calls each (rates + adaptive step), {acc} accepted cell-steps in {dt:.1f} s"}
+                      f"calls each (rates + adaptive step), {acc} accepted cell-steps in {dt:.1f} s "
+                      f"on {cores} threads; one thread: {calls1} calls, {acc1} cell-steps in "
+                      f"{dt1:.1f} s (the same calls from the same start, fewer of them)"}
 
 
 class Disc:
@@ -379,35 +404,39 @@ class Disc:
                     failed=int((status.cpu().numpy() != 0).sum()), rho=rho)
 
 
-def split_error(D, rho_start, sample):
-    """Split-BF16 step against the FP64 GPU step over the same steps, on a
-    sample of cells: FP64 ADAPTIVE call over 20 dt, then the split step
-    replays its accepted steps.  Resolved bins hold >= 1e-12 of the cell's
-    mass; the rest are reported relative to the cell's mass."""
+def split_error(D, sample, calls=20):
+    """Split-BF16 step against the FP64 oracle over the same steps, on a
+    sample of cells from the disc's initial state: one split call over
+    `calls` dt (ADAPTIVE, FP32 blocked rates, its own steps), then the oracle
+    replays those steps in FP64 with its own rates from the same start.
+    Resolved bins hold >= 1e-12 of the cell's mass; the rest are reported
+    relative to the cell's mass."""
+    import oracle as O
     torch, L = D.torch, D.L
     from paper_2402_18471_amd import disc
     idx = np.asarray(sample)
     sub = disc.subset_cells(D.d, idx)
     cells = {k: D.t(v) for k, v in sub["cells"].items()}
     vd, vf = D.t(sub["v_dust"]), D.t(sub["v_frag"])
-    rho0 = rho_start[D.t(idx, torch.int64)].contiguous()
-    dt = 20.0 * float(D.d["dt"])
-    K64 = D.ctx.coag_rates(cells, vd, vf)
+    rho0 = sub["rho"]
+    dt = calls * float(D.d["dt"])
     K32 = D.ctx.coag_rates_blocked(cells, vd, vf)
-    a = D.ctx.coag_step(rho0.clone(), *K64, dt, max_sub=512)
-    b = D.ctx.coag_step(rho0.clone(), *K32, dt, mode=L.REPLAY, prec=L.PREC_SPLIT_BF16,
-                        nsub=a["nsub"].clone(), h_log=a["h_log"])
+    b = D.ctx.coag_step(D.t(rho0), *K32, dt, prec=L.PREC_SPLIT_BF16, max_sub=1024)
     torch.cuda.synchronize()
-    x, ref = b["rho"].cpu().numpy(), a["rho"].cpu().numpy()
+    x, ns, hl = b["rho"].cpu().numpy(), b["nsub"].cpu().numpy(), b["h_log"].cpu().numpy()
+    g = O.make_grid(D.cfg.n_bins, D.cfg.s_min, D.cfg.s_max, rho_m=D.cfg.rho_m)
+    oKc, oKf = O.rates(g, sub["cells"], sub["v_dust"], sub["v_frag"])
+    ref = O.step(g, rho0, oKc, oKf, dt, mode=O.REPLAY, nsub=ns, h_log=hl)["rho"]
     M = ref.sum(1, keepdims=True)
     res = ref >= 1e-12 * M
     err = np.abs(x - ref)
-    return {"sample": f"{len(idx)} cells (every {D.C // len(idx)}th), state after the FP64 timed "
-                      f"calls, one call over 20 dt; split replays the FP64 path's steps",
+    return {"sample": f"{len(idx)} cells (every {D.C // len(idx)}th) from the initial state, one "
+                      f"split call over {calls} dt ({float(ns.mean()):.1f} accepted sub-steps per "
+                      "cell), replayed by the FP64 oracle",
             "max_rel_err_resolved_bins": float(np.max(err[res] / ref[res])),
             "max_abs_err_unresolved_bins_over_cell_mass": float(np.max((err / M)[~res]))
             if np.any(~res) else 0.0,
-            "max_total_mass_err": float(np.max(np.abs(x.sum(1) / rho0.cpu().numpy().sum(1) - 1))),
+            "max_total_mass_err": float(np.max(np.abs(x.sum(1) / rho0.sum(1) - 1))),
             "status_ok": bool(np.all(b["status"].cpu().numpy() == 0))}
 
 
@@ -531,7 +560,7 @@ def main():
             "ms_per_step": s["wall"] / K * 1e3, "rates_ms": float(s["rates_ms"].mean()),
             "step_ms": float(s["step_ms"].mean()), "cells_failed": s["failed"],
             "speedup_vs_fp64": (s["acc"] / s["wall"]) / (f["acc"] / f["wall"]),
-            "error_vs_fp64": split_error(D, f["rho"], np.arange(0, C, max(1, C // 512))),
+            "error_vs_oracle": split_error(D, np.arange(0, C, max(1, C // 512))),
         }
     free, total = torch.cuda.mem_get_info()
     out["device_memory_used_gb"] = (total - free) / 1e9    # rates, workspaces, torch cache

@@ -76,6 +76,7 @@ def _load():
                                                   _dp, ct.c_int, L, ct.c_double]),
             "oracle_cs_rhs_grad": (ct.c_double, [G, _dp, _dp, _dp, _dp, ct.c_int, L, ct.c_double]),
             "oracle_num_threads": (ct.c_int, []),
+            "oracle_set_num_threads": (None, [ct.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -300,3 +301,8 @@ def cs_rhs_grad(g: Grid, rho, Kc, Kf, mu, which, index, hcs=1e-30):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's loops over cells from now on."""
+    _load().oracle_set_num_threads(int(n))

@@ -685,6 +685,18 @@ int oracle_rates_deriv(const oracle_grid_t *g, long C, const oracle_cells_t *c,
     return 0;
 }
 
+/* Threads the OpenMP loops over cells use from now on (n >= 1); for the
+   single-thread timing of the CPU baseline. */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

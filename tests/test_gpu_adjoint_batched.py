@@ -15,11 +15,16 @@ Bars, per cell:
              gradient of a mean log size changes sign across the bins, so
              relative errors are taken against at least 5 % of the cell's
              largest component), and |dg| <= 1e-7 max|g| everywhere there
-  bins empty at the start: dJ/drho_k there is ill-conditioned (the oracle's
-      own gradient moves by ~1e-3 of the largest component when its inputs
-      are perturbed by 4e-16 relative: the terms it is made of cancel to 13
-      digits); the bound is 10x the oracle's spread over three such
-      perturbations of rho and g_out, plus 1e-12 max|g|
+  bins empty at the start: dJ/drho_k there is ill-conditioned (its terms
+      cancel to 13 digits): the FP64 oracle is 1e-3 .. 4e-3 of the cell's
+      largest component away from the exact-arithmetic value, so both sides
+      are held to the oracle's extended-precision adjoint (oracle/extended.py)
+      instead, per cell over those bins:
+        batched kernels   max|g - g_ld| <= 0.1 max|g_oracle - g_ld| + 1e-12 max|g|
+      (they fold the heavier grain's loss into the redistribution entries
+      before any product and are measured 60 .. 1000x closer than the
+      oracle); the per-cell kernel, which sums in the oracle's order, within
+      5x the oracle's largest distance over the cells
   alpha, v_frag: with S = max(|alpha dJ/dalpha|, |v_frag dJ/dv_frag|) the
       cell's largest logarithmic sensitivity, |x d(dJ/dx)| <= tol S, tol =
       1e-12 (FP64), 1e-6 (split).  (Where fragmentation is off, dJ/dv_frag is
@@ -84,19 +89,27 @@ def _oracle_call(O, g, d, rho, dt):
     return a, g_out, og, oa, ov
 
 
-def _envelope(O, g, d, rho, a, g_out, og, trials=3):
-    """Largest change of the oracle's density gradient, per cell over its bins
-    empty at the start, under 4e-16 relative noise on rho and on g_out."""
-    rng = np.random.default_rng(5)
-    env = np.zeros(len(rho))
-    for _ in range(trials):
-        r2 = rho * (1 + 4e-16 * rng.standard_normal(rho.shape))
-        go2 = g_out * (1 + 4e-16 * rng.standard_normal(g_out.shape))
-        g2, _, _ = O.step_backward(g, d["cells"], d["v_dust"], d["v_frag"], r2, 0.0,
-                                   a["h_log"], a["nsub"], go2)
-        empty = rho < 1e-12 * rho.sum(1, keepdims=True)
-        env = np.maximum(env, np.where(empty, np.abs(g2 - og), 0.0).max(1))
-    return env
+def _ld_adjoint(g, d, rho, a, g_out):
+    """The oracle's adjoint of the same call in extended precision."""
+    from oracle import extended
+    oKc, oKf = _oracle_rates(g, d)
+    r = extended.step_backward(g, d["cells"], d["v_dust"], d["v_frag"], rho, a["h_log"],
+                               a["nsub"], g_out, oKc, oKf)
+    return r["g_in"].astype(np.float64)
+
+
+def _oracle_rates(g, d):
+    import oracle as O
+    return O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
+
+
+def _empty_bound(rho, og, ld, factor):
+    """Per-cell bound over the bins empty at the start: factor times the
+    oracle's own largest distance from the extended-precision adjoint there,
+    plus 1e-12 of the cell's largest component."""
+    empty = rho < 1e-12 * rho.sum(1, keepdims=True)
+    scale = np.abs(ld).max(1)
+    return factor * np.where(empty, np.abs(og - ld), 0.0).max(1) + 1e-12 * scale, empty
 
 
 def _gpu_backward(ctx, d, rho, a, g_out, prec):
@@ -108,7 +121,7 @@ def _gpu_backward(ctx, d, rho, a, g_out, prec):
     return gi.cpu().numpy(), ga.cpu().numpy(), gv.cpu().numpy()
 
 
-def _check(d, rho, og, oa, ov, env, gi, ga, gv, split):
+def _check(d, rho, og, oa, ov, ld, gi, ga, gv, split):
     scale = np.abs(og).max(1, keepdims=True)
     res = rho >= 1e-12 * rho.sum(1, keepdims=True)
     err = np.abs(gi - og)
@@ -118,8 +131,10 @@ def _check(d, rho, og, oa, ov, env, gi, ga, gv, split):
     else:
         bound = 1e-12 * np.abs(og) + 1e-15 * scale
     assert np.all(err[res] <= bound[res]), np.max((err / np.maximum(np.abs(og), 1e-300))[res])
-    env_b = 10.0 * env[:, None] + 1e-12 * scale
-    assert np.all((err <= env_b)[~res]), np.max((err / env_b)[~res])
+    if ld is not None:
+        eb, empty = _empty_bound(rho, og, ld, 0.1)
+        got = np.where(empty, np.abs(gi - ld), 0.0).max(1)
+        assert np.all(got <= eb), np.max(got / eb)
     al, vf = d["cells"]["alpha"], d["v_frag"]
     S = np.maximum(np.abs(al * oa), np.abs(vf * ov))
     tol = 1e-6 if split else 1e-12
@@ -134,10 +149,10 @@ def test_adjoint_one_call_against_oracle(O, case, prec):
     cfg, g, d, (m, me, s) = _setup(O, case)
     rho = d["rho"]
     a, g_out, og, oa, ov = _oracle_call(O, g, d, rho, d["dt"] * 5)
-    env = _envelope(O, g, d, rho, a, g_out, og)
+    ld = _ld_adjoint(g, d, rho, a, g_out)
     ctx = _ctx(m, me, s, cfg.rho_m)
     gi, ga, gv = _gpu_backward(ctx, d, rho, a, g_out, prec)
-    _check(d, rho, og, oa, ov, env, gi, ga, gv, prec == 1)
+    _check(d, rho, og, oa, ov, ld, gi, ga, gv, prec == 1)
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "split"])
@@ -159,7 +174,7 @@ def test_adjoint_ragged_batches_well_conditioned(O, prec):
                                  a["h_log"], a["nsub"], g_out)
     ctx = _ctx(m, me, s, cfg.rho_m)
     gi, ga, gv = _gpu_backward(ctx, d, rho, a, g_out, prec)
-    _check(d, rho, og, oa, ov, np.zeros(len(rho)), gi, ga, gv, prec == 1)
+    _check(d, rho, og, oa, ov, None, gi, ga, gv, prec == 1)
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "split"])
@@ -227,3 +242,46 @@ def test_zero_steps_pass_the_cotangent_through(O):
         torch.cuda.synchronize()
         assert torch.equal(gbuf, g0)
         assert torch.all(ga == 0) and torch.all(gv == 0)
+
+
+def test_batched_and_per_cell_adjoints_agree_on_the_100_bin_grid(O):
+    """The batched adjoint (16 cells per workgroup, matrix cores) and the
+    per-cell one (COAG_STEP_KERNEL=cell: one workgroup per cell, its own
+    replay, dJ/dK per pair) on 35 cells of the 100-bin disc (two whole
+    batches and a ragged one), one call: populated bins to 1e-12 relative;
+    bins empty at the start against the extended-precision adjoint, the
+    batched kernel within 0.1x the oracle's own distance from it per cell,
+    the per-cell one within 5x its largest distance over the cells."""
+    from paper_2402_18471_amd.coag import coag_create
+    cfg, g, d, (m, me, s) = _setup(O, ("disc64x32_n100", 5, 7, None))
+    rho = d["rho"]
+    a, g_out, og, oa, ov = _oracle_call(O, g, d, rho, d["dt"] * 5)
+    ld = _ld_adjoint(g, d, rho, a, g_out)
+    old = os.environ.get("COAG_STEP_KERNEL")
+    os.environ["COAG_STEP_KERNEL"] = "cell"
+    try:
+        cell_ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
+    finally:
+        if old is None:
+            os.environ.pop("COAG_STEP_KERNEL", None)
+        else:
+            os.environ["COAG_STEP_KERNEL"] = old
+    gb, ab, vb = _gpu_backward(_ctx(m, me, s, cfg.rho_m), d, rho, a, g_out, 0)
+    gc, ac, vc = _gpu_backward(cell_ctx, d, rho, a, g_out, 0)
+    scale = np.abs(gc).max(1, keepdims=True)
+    res = rho >= 1e-12 * rho.sum(1, keepdims=True)
+    err = np.abs(gb - gc)
+    assert np.all((err <= 1e-12 * np.abs(gc) + 1e-15 * scale)[res])
+    eb, empty = _empty_bound(rho, og, ld, 0.1)
+    e = np.where(empty, np.abs(gb - ld), 0.0).max(1)
+    assert np.all(e <= eb), np.max(e / eb)
+    # the per-cell kernel: within 5x the oracle's largest distance over the cells
+    # (its error and the oracle's are of one kind, FP64 in the literal order, so
+    # a single cell can find the oracle luckier than itself)
+    e_cell = np.where(empty, np.abs(gc - ld), 0.0).max()
+    e_ora = np.where(empty, np.abs(og - ld), 0.0).max()
+    assert e_cell <= 5.0 * e_ora, e_cell / e_ora
+    al, vf = d["cells"]["alpha"], d["v_frag"]
+    S = np.maximum(np.abs(al * ac), np.abs(vf * vc))
+    assert np.all(np.abs(al * (ab - ac)) <= 1e-12 * S)
+    assert np.all(np.abs(vf * (vb - vc)) <= 1e-12 * S)

@@ -11,10 +11,13 @@ cells (central differences at h = 1e-6 carry O(h^2) truncation and ~1e-9
 rounding); the oracle's final states to 1e-9 relative (floor 1e-15 of the
 cell's mass), its alpha and v_frag gradients to 1e-6 relative, its density
 gradient to 1e-6 of the cell's largest component in the bins populated at the
-start.  In the bins empty at the start (grains above 1 um), dJ/drho_k is
-ill-conditioned on the 18-decade grid: FP64 evaluations in different orders
-(oracle, GPU) differ there by up to ~1e-3 of the largest component, which the
-test bounds at 1e-2.
+start.  In the bins empty at the start (grains above 1 um) dJ/drho_k is
+ill-conditioned on the 18-decade grid: the FP64 oracle's chained gradient is
+up to ~2e-3 of the cell's largest component away from the exact-arithmetic
+value there.  On two of the 16 cells both are compared with the oracle's
+extended-precision chain (oracle/extended.py, long double, 200 calls): the
+GPU within 1e-5 of the cell's largest component (measured ~1e-6; the
+long-double chain itself moves by ~5e-8 when its summation order changes).
 """
 import numpy as np
 import pytest
@@ -97,20 +100,25 @@ def test_full_adjoint_against_oracle_on_16_cells(setup, O):
     out = _fwd(ctx, d, rho0, al, vf, idx)
     _Jc(out, _t(lns)).sum().backward()
     g = O.make_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
-    Kc, Kf = O.rates(g, sub["cells"], sub["v_dust"], sub["v_frag"])
-    states, logs, r = [], [], sub["rho"].copy()
-    for _ in range(CALLS):
-        states.append(r)
-        a = O.step(g, r, Kc, Kf, d["dt"], mode=O.FIXED, nsub=NSUB, max_sub=NSUB)
-        r, _ = a["rho"], logs.append(a["h_log"])
-    Jc = (r * lns).sum(1) / r.sum(1)
-    gr = (lns[None, :] - Jc[:, None]) / r.sum(1, keepdims=True)
-    ga, gv = np.zeros(len(idx)), np.zeros(len(idx))
-    for s in range(CALLS - 1, -1, -1):
-        gr, a_s, v_s = O.step_backward(g, sub["cells"], sub["v_dust"], sub["v_frag"], states[s],
-                                       d["dt"], logs[s], np.full(len(idx), NSUB), gr)
-        ga += a_s
-        gv += v_s
+    def chain(r0):
+        Kc, Kf = O.rates(g, sub["cells"], sub["v_dust"], sub["v_frag"])
+        states, logs, r = [], [], r0.copy()
+        for _ in range(CALLS):
+            states.append(r)
+            a = O.step(g, r, Kc, Kf, d["dt"], mode=O.FIXED, nsub=NSUB, max_sub=NSUB)
+            r, _ = a["rho"], logs.append(a["h_log"])
+        Jc = (r * lns).sum(1) / r.sum(1)
+        gr = (lns[None, :] - Jc[:, None]) / r.sum(1, keepdims=True)
+        ga, gv = np.zeros(len(idx)), np.zeros(len(idx))
+        for s in range(CALLS - 1, -1, -1):
+            gr, a_s, v_s = O.step_backward(g, sub["cells"], sub["v_dust"], sub["v_frag"],
+                                           states[s], d["dt"], logs[s], np.full(len(idx), NSUB),
+                                           gr)
+            ga += a_s
+            gv += v_s
+        return gr, ga, gv, r
+
+    gr, ga, gv, r = chain(sub["rho"])
     x = out.detach().cpu().numpy()
     assert np.all(np.abs(x - r) <= 1e-9 * np.abs(r) + 1e-15 * r.sum(1, keepdims=True))
     np.testing.assert_allclose(al.grad.cpu().numpy(), ga, rtol=1e-6, atol=1e-6 * np.abs(ga).max())
@@ -120,6 +128,20 @@ def test_full_adjoint_against_oracle_on_16_cells(setup, O):
     err = np.abs(gi - gr) / sc
     held = sub["rho"] > 0                          # bins populated at the start
     assert np.all(err[held] <= 1e-6), np.max(err[held])
-    # bins empty at the start: their sensitivity spans the grid's 18 decades of
-    # mass and differs between FP64 evaluation orders far more than the rest
-    assert np.all(err <= 1e-2), np.max(err)
+    # bins empty at the start: against the extended-precision chain on two cells
+    from oracle import extended
+    two = np.array([0, 9])
+    cells2 = {k: v[two] for k, v in sub["cells"].items()}
+    ext = extended.Extended(g, *O.rates(g, cells2, sub["v_dust"][two], sub["v_frag"][two]))
+    steps = np.full((2, CALLS * NSUB), d["dt"] / NSUB)
+    y = ext.step(sub["rho"][two], steps, np.full(2, CALLS * NSUB))
+    M = y.sum(1, keepdims=True)
+    g_end = (lns[None, :] - (y * lns).sum(1, keepdims=True) / M) / M
+    ld = ext.step_backward(sub["rho"][two], steps, np.full(2, CALLS * NSUB),
+                           g_end)["g_in"].astype(np.float64)
+    sc2 = np.abs(ld).max(1, keepdims=True)
+    e_gpu = (np.abs(gi[two] - ld) / sc2)[~held[two]]
+    e_ora = (np.abs(gr[two] - ld) / sc2)[~held[two]]
+    print(f"bins empty at the start, against long double: GPU {e_gpu.max():.2e}, "
+          f"oracle {e_ora.max():.2e} of the cell's largest component")
+    assert np.all(e_gpu <= 1e-5), e_gpu.max()

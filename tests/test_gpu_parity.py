@@ -10,19 +10,22 @@ distribution, device exp/sqrt vs libm), so results agree to a few ulp of the
 gross terms that make them up:
   rates        |dK| <= 1e-12 (Kc + Kf)
   rhs          |df_k| <= 1e-12 (gain_k + loss_k)
-  step         |drho_k| <= 1e-12 rho_k + 1e-13 dt (gain_k + loss_k) + 1e-14 atol
-               (atol = 1e-10 sum rho; gain, loss at the start state).  The middle
-               term is the rounding bound of evaluating gain - loss: where the two
-               nearly cancel (a heavy bin sweeping up light grains keeps almost all
-               of the product mass, most of all in the clipped top bin) any FP64
-               evaluation of the right-hand side, the oracle's included, carries
-               an error of eps (gain + loss) that the step multiplies by h.
-               Where even that is not enough (a bin whose value the dynamics
-               amplifies, e.g. heavy bins fed by the clipped top bin), the bound
-               also admits 30x the oracle's own spread under 4e-16 relative noise
-               on its input state ("noise envelope"): the GPU may not differ from
-               the oracle by more than the oracle differs from itself when its
-               input is rounded differently.
+  step         against the oracle's extended-precision evaluation of the same
+               steps (oracle/extended.py: the oracle's tables and rates, long
+               double arithmetic), with
+                 base = 1e-12 |rho_k| + 1e-13 dt (gain_k + loss_k) + 1e-14 atol
+               (atol = 1e-10 sum rho; gain, loss at the start state): the
+               rounding bound of evaluating gain - loss, which nearly cancel in
+               heavy bins sweeping up light grains.
+                 batched kernel   |rho_gpu - rho_ld| <= 0.05 base
+                 per-cell kernel  |rho_gpu - rho_ld| <= base + |rho_oracle - rho_ld|
+               The batched kernel folds the heavier grain's loss into the
+               redistribution entries before any product (an exact FP64
+               difference), so it carries far less of that rounding than the
+               oracle's literal order (measured: <= 0.0023 base, where the
+               oracle reaches 7 base on a start populated in every bin); the
+               per-cell kernels sum in the oracle's way and are held to be no
+               farther from the exact-arithmetic result than the oracle is.
   adjoint      |dg| <= 1e-9 max|g| on a well-conditioned grid
 """
 import os
@@ -126,21 +129,20 @@ def test_rhs_parity(O, case, chi_split):
         assert np.all(np.abs(_np(f).sum(1)) <= 1e-13 * gain.sum(1))
 
 
-def _step_tol(gpu, ora, rho0, gl_dt, env=0.0):
-    """gl_dt: dt * (gain + loss) of the oracle's right-hand side at rho0;
-    env: the oracle's noise envelope (see module docstring)."""
+def _ld_steps(g, Kc, Kf, rho0, h_log, nsub):
+    """The same steps in the oracle's extended-precision evaluation."""
+    from oracle import extended
+    return extended.Extended(g, Kc, Kf).step(rho0, h_log, nsub).astype(np.float64)
+
+
+def _step_ok(gpu, ora, ld, rho0, gl_dt, kernel):
+    """Per-bin step bar against the extended-precision result (module
+    docstring); returns the boolean array."""
     atol = 1e-10 * rho0.sum(1, keepdims=True)
-    return np.abs(gpu - ora) <= 1e-12 * np.abs(ora) + 1e-13 * gl_dt + 30.0 * env + 1e-14 * atol
-
-
-def _envelope(run, rho0, trials=3):
-    """Max deviation of run(rho0 * (1 + 4e-16 xi)) from run(rho0), xi ~ N(0,1)."""
-    ref = run(rho0)
-    rng = np.random.default_rng(123)
-    env = np.zeros_like(ref)
-    for _ in range(trials):
-        env = np.maximum(env, np.abs(run(rho0 * (1 + 4e-16 * rng.standard_normal(rho0.shape))) - ref))
-    return ref, env
+    base = 1e-12 * np.abs(ld) + 1e-13 * gl_dt + 1e-14 * atol
+    if kernel == "batch":
+        return np.abs(gpu - ld) <= 0.05 * base
+    return np.abs(gpu - ld) <= base + np.abs(ora - ld)
 
 
 def _gl_dt(O, g, rho0, Kc, Kf, dt):
@@ -172,9 +174,9 @@ def test_step_fixed_parity(O, case, kernel):
         r = ctx.coag_step(rho, _t(oKc), _t(oKf), dt, mode=1, nsub=nsub, max_sub=8)
         torch.cuda.synchronize()
         o = O.step(g, rho0, oKc, oKf, dt, mode=O.FIXED, nsub=n)
-        _, env = _envelope(lambda x: O.step(g, x, oKc, oKf, dt, mode=O.FIXED, nsub=n)["rho"], rho0)
-        ok = _step_tol(_np(r["rho"]), o["rho"], rho0, _gl_dt(O, g, rho0, oKc, oKf, dt), env)
-        assert np.all(ok), np.max(np.abs(_np(r["rho"]) - o["rho"]) / (np.abs(o["rho"]) + 1e-300))
+        ld = _ld_steps(g, oKc, oKf, rho0, o["h_log"], o["nsub"])
+        ok = _step_ok(_np(r["rho"]), o["rho"], ld, rho0, _gl_dt(O, g, rho0, oKc, oKf, dt), kernel)
+        assert np.all(ok), np.max(np.abs(_np(r["rho"]) - ld) / (np.abs(ld) + 1e-300))
         assert np.all(_np(r["status"]) == 0)
         np.testing.assert_array_equal(_np(r["h_log"])[:, :n], o["h_log"][:, :n])
 
@@ -200,9 +202,11 @@ def test_batched_step_other_crater_yields(O, chi):
     r = ctx.coag_step(_t(rho0), blocked(oKc), blocked(oKf), dt, mode=1,
                       nsub=_t(np.full(C, n), torch.int32), max_sub=8)
     torch.cuda.synchronize()
-    o, env = _envelope(lambda x: O.step(g, x, oKc, oKf, dt, mode=O.FIXED, nsub=n)["rho"], rho0)
+    o = O.step(g, rho0, oKc, oKf, dt, mode=O.FIXED, nsub=n)
+    ld = _ld_steps(g, oKc, oKf, rho0, o["h_log"], o["nsub"])
     assert np.all(_np(r["status"]) == 0)
-    assert np.all(_step_tol(_np(r["rho"]), o, rho0, _gl_dt(O, g, rho0, oKc, oKf, dt), env))
+    assert np.all(_step_ok(_np(r["rho"]), o["rho"], ld, rho0, _gl_dt(O, g, rho0, oKc, oKf, dt),
+                           "batch"))
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
@@ -222,9 +226,9 @@ def test_step_adaptive_parity_by_replay(O, case, kernel):
     torch.cuda.synchronize()
     st, ns, hl = _np(r["status"]), _np(r["nsub"]), _np(r["h_log"])
     assert np.all(st == 0)
-    o, env = _envelope(lambda x: O.step(g, x, oKc, oKf, dt, mode=O.REPLAY, nsub=ns, h_log=hl)["rho"],
-                       rho0)
-    assert np.all(_step_tol(_np(r["rho"]), o, rho0, _gl_dt(O, g, rho0, oKc, oKf, dt), env))
+    o = O.step(g, rho0, oKc, oKf, dt, mode=O.REPLAY, nsub=ns, h_log=hl)["rho"]
+    ld = _ld_steps(g, oKc, oKf, rho0, hl, ns)
+    assert np.all(_step_ok(_np(r["rho"]), o, ld, rho0, _gl_dt(O, g, rho0, oKc, oKf, dt), kernel))
     oa = O.step(g, rho0, oKc, oKf, dt, max_sub=256)
     same = (oa["nsub"] == ns) & (oa["nrej"] == _np(r["nrej"]))
     assert same.mean() >= 0.99
@@ -234,6 +238,42 @@ def test_step_adaptive_parity_by_replay(O, case, kernel):
     # mass conservation
     m0, m1 = rho0.sum(1), _np(r["rho"]).sum(1)
     assert np.max(np.abs(m1 / m0 - 1)) < 1e-13
+
+
+def test_all_cells_of_the_64x32_disc_over_calls_replayed_by_oracle(O):
+    """The whole 64x32-cell, 100-bin disc (2048 cells), three ADAPTIVE calls
+    of dt = 10 yr on the batched FP64 step, the state carried from call to
+    call; the oracle replays the GPU's step sequence of each call from its own
+    state at the call's start.  Every cell: GPU within the rounding bar of
+    the oracle's FP64 result; every eighth cell (256): GPU within the batched
+    kernel's bar of the oracle's extended-precision chain."""
+    cfg, g, d, ctx, cells = _case(O, "disc64x32_n100", 64, 32, None, kernel="batch")
+    oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
+    dt = d["dt"]
+    rho_g = _t(d["rho"])
+    h = torch.zeros(cfg.n_cells, dtype=torch.float64, device=DEV)
+    logs, gpu_states = [], []
+    for _ in range(3):
+        r = ctx.coag_step(rho_g, _t(oKc), _t(oKf), dt, h=h, max_sub=256)
+        torch.cuda.synchronize()
+        assert np.all(_np(r["status"]) == 0)
+        logs.append((_np(r["nsub"]).copy(), _np(r["h_log"]).copy()))
+        gpu_states.append(_np(rho_g).copy())
+    from oracle import extended
+    sel = np.arange(0, cfg.n_cells, 8)
+    ext = extended.Extended(g, oKc[sel], oKf[sel])
+    x, xl = d["rho"], d["rho"][sel].astype(np.longdouble)
+    for k, (ns, hl) in enumerate(logs):
+        xo = O.step(g, x, oKc, oKf, dt, mode=O.REPLAY, nsub=ns, h_log=hl)["rho"]
+        xl = ext.step(xl, hl[sel], ns[sel])
+        gl = _gl_dt(O, g, x, oKc, oKf, dt)
+        base = 1e-12 * np.abs(xo) + 1e-13 * gl + 1e-14 * 1e-10 * x.sum(1, keepdims=True)
+        ok = np.abs(gpu_states[k] - xo) <= base
+        assert np.all(ok), (k, np.argwhere(~ok)[:5])
+        ld = xl.astype(np.float64)
+        assert np.all(_step_ok(gpu_states[k][sel], xo[sel], ld, x[sel], gl[sel], "batch")), k
+        x = xo
+    assert sum(int(ns.sum()) for ns, _ in logs) > 2 * cfg.n_cells
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
