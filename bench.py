@@ -14,7 +14,9 @@ Measured on the 256x128-cell, 150-bin disc:
                  FP64 path, and its per-bin error against the FP64 oracle
                  (replaying the split call's steps) on a stratified sample of cells
   adjoint        coag_step_backward time over forward (rates + step) time on
-                 the 64x32-cell, 100-bin disc, FP64 and split BF16
+                 the 64x32-cell, 100-bin disc, FP64 and split BF16 (and on
+                 the bench disc, where the batched adjoint fills the GPU),
+                 with the backward's algorithmic HBM bytes over its time
   roofline       the FP64 step kernel against HBM bandwidth: algorithmic
                  bytes = (16 P + 16 N) per cell per right-hand side
   cpu_baseline   the CPU oracle on a sample of the same workload
@@ -38,26 +40,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 KERNEL_SRC = os.path.join(ROOT, "paper_2402_18471_amd", "csrc", "coag_batch.hip")
-COUNTERS = os.path.join(ROOT, "profiles", "k_step_batch_counters.json")
-
-
-def profiled_traffic(rhs_per_launch, kind):
-    """HBM bytes per launch of the batched step kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, calibrated on a
-    device copy of known size, per cell right-hand side), or None when there
-    is none or the kernel source has changed since the counters were taken."""
-    import hashlib
-    try:
-        with open(COUNTERS) as f:
-            c = json.load(f)
-        with open(KERNEL_SRC, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
-    except OSError:
-        return None
-    if c.get("kernel_source_sha256") != sha or kind not in c:
-        return None
-    per = c[kind]["fetch_bytes_per_cell_rhs"] + c[kind]["write_bytes_per_cell_rhs"]
-    return float(np.mean(rhs_per_launch) * per / 1e9)
+COUNTERS = os.path.join(ROOT, "profiles", "kernel_counters.json")
 
 
 def progress(msg):
@@ -102,11 +85,14 @@ def parse():
     ap.add_argument("--evolve-calls", type=int, default=20)
     ap.add_argument("--evolve-ckpt", type=int, default=20)
     ap.add_argument("--evolve-prec", choices=("fp64", "split"), default="split")
-    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_LOG"),
-                    help="no GPU work: write the counter summary the roofline's traffic is read "
-                         "from, from the counter_collection.csv files of a FETCH_SIZE and a "
-                         "WRITE_SIZE rocprofv3 pass over 'bench.py --steps 1 --warmup 1 "
-                         "--no-cpu-baseline --no-adjoint --calibrate-copy', and that run's output")
+    ap.add_argument("--summarize-counters", nargs="+",
+                    metavar="OUT_JSON BENCH_LOG TRACE_CSV PMC_CSV",
+                    help="no GPU work: write the per-kernel counter summary (the roofline's "
+                         "traffic is read from it) from the output of a 'bench.py --steps 1 "
+                         "--warmup 1 --no-cpu-baseline --calibrate-copy' run, a rocprofv3 kernel "
+                         "trace of the bench, and the counter_collection.csv files of rocprofv3 "
+                         "passes over that run (FETCH_SIZE, WRITE_SIZE, issue counters, FP64 "
+                         "instruction counters)")
     return ap.parse_args()
 
 
@@ -119,8 +105,9 @@ def evolve_memory_plan(C, N, calls, ckpt, width, prec_split):
     FP32 for split; FP64 [C][P] plus the step's reordered copy for FP64), the
     step's slope workspace, the adjoint's slab workspace (the library's rule:
     rates, their derivative factors, step starts and stage states of `width`
-    steps, replay state, slopes and v3 for as many whole 16-cell batches as
-    fit ADJ_BUDGET, all cells if they fit), checkpoints every ckpt calls, the
+    steps, replay state, slopes and v3 for the fewest equal slabs of whole
+    16-cell batches that fit ADJ_BUDGET, all cells if they fit), checkpoints
+    every ckpt calls, the
     compacted step logs (width per call, an upper bound) and step counts,
     one segment's start states, and the state, its gradient and g_out."""
     P = N * (N + 1) // 2
@@ -135,8 +122,12 @@ def evolve_memory_plan(C, N, calls, ckpt, width, prec_split):
         return (2 * al(rt * P * Sb) + 2 * al(gt * P * Sb) + al(8 * N * (width + 1) * S) +
                 al(8 * N * 2 * width * S) + al(8 * N * S) + al(Sb * 5 * N * 8) + al(4 * S) +
                 al(8 * N * S))
-    S = C if adj(C) <= ADJ_BUDGET else max(4096, ADJ_BUDGET // adj(16) * 16)
-    S = min(S, C)
+    if adj(C) <= ADJ_BUDGET:
+        S = C
+    else:
+        smax = max(4096, ADJ_BUDGET // adj(16) * 16)
+        nslab = -(-C // smax)
+        S = min(C, -(-(-(-C // nslab)) // 16) * 16)
     state = C * N * 8
     plan = {"rates_one_call": rates, "step_workspace": slopes, "adjoint_slab_cells": S,
             "adjoint_workspace": adj(S), "checkpoints": -(-calls // ckpt) * state,
@@ -220,46 +211,128 @@ def evolve(args):
         "data": "synthetic disc, forward = coag_rates + ADAPTIVE coag_step per call"}), flush=True)
 
 
-def summarize_counters(fetch_csv, write_csv, bench_log):
-    """Per-cell-RHS HBM bytes of the two step forms from rocprofv3 counter
-    passes over one 'bench.py --steps 1 --warmup 1 --calibrate-copy' run.
-    Each form launches the step kernel three times there (warm-up call, timed
-    call, error sample); the timed call is the second.  FETCH_SIZE and
-    WRITE_SIZE (KiB per dispatch) are scaled by what they read for the final
-    1 GiB device copy."""
+def _kernel_short(name):
+    """Kernel name without return type, namespaces and arguments."""
+    import re
+    n = name.replace("void ", "").replace("(anonymous namespace)::", "").replace("coag::", "")
+    return re.sub(r"\(.*", "", n).strip()
+
+
+def summarize_counters(out_json, bench_log, trace_csv, *pmc_csvs):
+    """Per-kernel counter summary of rocprofv3 passes over one 'bench.py
+    --steps 1 --warmup 1 --no-cpu-baseline --calibrate-copy' run (FETCH_SIZE,
+    WRITE_SIZE, issue counters, FP64 instruction counters; one pass each), with
+    durations from a kernel trace of the bench.  Launches are grouped by
+    kernel and grid size (the bench disc's launches, the adjoint's slabs and
+    the small samples have different grids); per group the mean per launch,
+    and for the step kernels the timed (second) launch.  FETCH_SIZE and
+    WRITE_SIZE (KiB) are scaled by what they read for the final 1 GiB device
+    copy; busy fractions are per SIMD: cycles = GRBM_GUI_ACTIVE / 8 XCDs,
+    1024 SIMDs, 4 cycles per wave64 VALU instruction; FP64 FLOPs =
+    64 (ADD + MUL + TRANS + 2 FMA) instructions."""
     import csv
     import hashlib
-
-    def per_dispatch(path):
-        rows = {}
+    counters = {}                   # (kernel, grid) -> list over launches of {counter: value}
+    order = {}
+    for path in pmc_csvs:
+        per = {}
         for r in csv.DictReader(open(path)):
-            rows.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
-        return [rows[k] for k in sorted(rows)]
+            d = per.setdefault(int(r["Dispatch_Id"]),
+                               {"k": (_kernel_short(r["Kernel_Name"]), int(r["Grid_Size"]))})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        seen = {}
+        for did in sorted(per):
+            d = per[did]
+            key = d.pop("k")
+            idx = seen[key] = seen.get(key, -1) + 1
+            slot = counters.setdefault(key, [])
+            while len(slot) <= idx:
+                slot.append({})
+            slot[idx].update(d)
+            order.setdefault(key, did)
+    dur = {}
+    for r in csv.DictReader(open(trace_csv)):
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        key = (_kernel_short(r["Kernel_Name"]), grid)
+        dur.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    copies = [c for (k, gsz), L in counters.items() if k == "__amd_rocclr_copyBuffer" for c in L
+              if "FETCH_SIZE" in c]
+    cal = max(copies, key=lambda c: c["FETCH_SIZE"])
+    f_fac = (1 << 30) / (cal["FETCH_SIZE"] * 1024.0)
+    w_cal = max((c for (k, gsz), L in counters.items() if k == "__amd_rocclr_copyBuffer" for c in L
+                 if "WRITE_SIZE" in c), key=lambda c: c["WRITE_SIZE"])
+    w_fac = (1 << 30) / (w_cal["WRITE_SIZE"] * 1024.0)
+    b = json.loads([ln for ln in open(bench_log) if ln.startswith("{")][-1])
+    src = os.path.join(ROOT, "paper_2402_18471_amd", "csrc")
+    shas = {f: hashlib.sha256(open(os.path.join(src, f), "rb").read()).hexdigest()
+            for f in ("coag_batch.hip", "coag_adjoint.hip", "coag_kernels.hip", "coag_rate.h")}
+    out = {"kernel_sources_sha256": shas,
+           "workload": f"{b['config']['workload']} (bench.py --steps 1 --warmup 1); adjoint "
+                       "kernels from its adjoint legs", "calibration": {
+               "copy_bytes": 1 << 30, "FETCH_SIZE_KiB": cal["FETCH_SIZE"], "fetch_factor": f_fac,
+               "WRITE_SIZE_KiB": w_cal["WRITE_SIZE"], "write_factor": w_fac},
+           "groups": []}
+    for key in sorted(counters, key=lambda k: order[k]):
+        name, grid = key
+        if not any(t in name for t in ("k_step_batch", "k_rates", "k_adj", "k_rate_derivs")):
+            continue
+        L = counters[key]
 
-    line = [ln for ln in open(bench_log) if ln.startswith("{")][-1]
-    b = json.loads(line)
-    rhs = {"fp64": b["rhs_per_call"], "split": b["split_bf16"]["rhs_per_call"]}
-    out = {"kernel_source": os.path.relpath(KERNEL_SRC, ROOT),
-           "kernel_source_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest(),
-           "workload": f"{b['config']['workload']}, second coagulation call from the MRN start "
-                       "(bench.py --steps 1 --warmup 1)",
-           "cell_rhs_in_profiled_launch": rhs, "calibration": {"copy_bytes": 1 << 30}}
-    cal = out["calibration"]
-    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        d = per_dispatch(path)
-        copy = [v for k, v in d if "copyBuffer" in k][-1]
-        cal[name + "_KiB"] = copy
-        factor = cal["copy_bytes"] / (copy * 1024.0)
-        cal[("fetch" if name == "FETCH_SIZE" else "write") + "_factor"] = factor
-        for kind, tag in (("fp64", "k_step_batch<0"), ("split", "k_step_batch<1")):
-            launches = [v for k, v in d if tag in k]
-            if len(launches) != 3:
-                raise SystemExit(f"{path}: expected 3 {tag} launches, found {len(launches)}")
-            key = ("fetch" if name == "FETCH_SIZE" else "write") + "_bytes_per_cell_rhs"
-            out.setdefault(kind, {})[key] = launches[1] * 1024.0 * factor / rhs[kind]
-    with open(COUNTERS, "w") as f:
+        def mean(c, sel=None):
+            v = [x[c] for x in (L if sel is None else [L[sel]]) if c in x]
+            return float(np.mean(v)) if v else None
+        g = {"kernel": name, "grid_threads": grid, "launches": len(L),
+             "trace_ms_mean": float(np.mean(dur[key])) if key in dur else None}
+        sel = 1 if name.startswith("k_step_batch") and len(L) > 1 else None
+        g["counted_launch"] = "second (the timed call)" if sel == 1 else "mean over launches"
+        if mean("FETCH_SIZE", sel) is not None:
+            g["fetch_bytes"] = mean("FETCH_SIZE", sel) * 1024.0 * f_fac
+        if mean("WRITE_SIZE", sel) is not None:
+            g["write_bytes"] = mean("WRITE_SIZE", sel) * 1024.0 * w_fac
+        grbm = mean("GRBM_GUI_ACTIVE", sel)
+        if grbm:
+            cyc = grbm / 8.0
+            g["counter_ms"] = cyc / 2.4e6
+            if mean("SQ_INSTS_VALU", sel) is not None:
+                g["valu_busy"] = mean("SQ_INSTS_VALU", sel) * 4.0 / (1024.0 * cyc)
+                g["mfma_busy"] = mean("SQ_VALU_MFMA_BUSY_CYCLES", sel) / (1024.0 * cyc)
+                g["valu_instr"] = mean("SQ_INSTS_VALU", sel)
+                g["mfma_instr"] = mean("SQ_INSTS_MFMA", sel)
+                g["lds_instr"] = mean("SQ_INSTS_LDS", sel)
+            f64 = [mean(c, sel) for c in ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+                                           "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU_FMA_F64")]
+            if all(x is not None for x in f64):
+                g["fp64_flop"] = 64.0 * (f64[0] + f64[1] + f64[2] + 2.0 * f64[3])
+        out["groups"].append(g)
+    out["bench_rhs_per_call"] = {"fp64": b["rhs_per_call"], "split": b["split_bf16"]["rhs_per_call"]}
+    with open(out_json, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
+
+
+def profiled_traffic(rhs_per_launch, kind):
+    """HBM bytes per launch of the batched step kernel (FP64 or split form) on
+    the bench disc from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE of the timed launch, calibrated on a device copy, scaled per
+    cell right-hand side), or None when there is none or the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if c.get("kernel_sources_sha256", {}).get("coag_batch.hip") != sha:
+        return None
+    want = "k_step_batch<0, double, true>" if kind == "fp64" else "k_step_batch<1, float, true>"
+    grp = [g for g in c["groups"] if g["kernel"] == want and "fetch_bytes" in g]
+    if not grp:
+        return None
+    g = max(grp, key=lambda x: x["grid_threads"])
+    per = (g["fetch_bytes"] + g["write_bytes"]) / c["bench_rhs_per_call"][kind]
+    return float(np.mean(rhs_per_launch) * per / 1e9)
 
 
 def cpu_model():
@@ -440,20 +513,25 @@ def split_error(D, sample, calls=20):
             "status_ok": bool(np.all(b["status"].cpu().numpy() == 0))}
 
 
-def adjoint_ratio(torch, reps=3):
-    """Backward / forward time of the same coagulation call on the 64x32 x 100
-    adjoint disc, in FP64 and in split BF16: the first call from the initial
-    state (rates + ADAPTIVE step, steps recorded; the split form with FP32
-    blocked rates), then coag_step_backward of that call in the same
-    precision (which recomputes the rates and their derivative factors and
-    replays the stage states); HIP events on the stream, mean over reps after
-    one warm-up."""
+def adjoint_ratio(torch, workload, reps=3):
+    """Backward / forward time of the same coagulation call on `workload`, in
+    FP64 and in split BF16: the first call from the initial state (rates +
+    ADAPTIVE step, steps recorded; the split form with FP32 blocked rates),
+    then coag_step_backward of that call in the same precision (which
+    recomputes the rates and their derivative factors, replays the stage
+    states and runs the reverse sweep); HIP events on the stream, mean over
+    reps after one warm-up.  Also the backward's algorithmic HBM bytes over
+    its time: per cell, the rates and derivative factors written once
+    (2 + 2 arrays of P), the replay's 1 + 3 n right-hand sides (rates and
+    state read), the sweep's 3 n transposed ones (rates, derivative factors,
+    stage state, cotangents), n = accepted steps of the cell."""
     from paper_2402_18471_amd import _lib as L
-    D = Disc("disc64x32_n100_adj", torch)
+    D = Disc(workload, torch)
     rho_in = D.t(D.d["rho"])
     dt = float(D.d["dt"])
+    P, N = D.P, D.N
     g_out = torch.ones((D.C, D.N), dtype=torch.float64, device=D.dev) / rho_in.sum(1, keepdim=True)
-    out = {"workload": D.cfg.name}
+    out = {"workload": D.cfg.name, "cells": D.C}
     for name, prec in (("fp64", L.PREC_FP64), ("split_bf16", L.PREC_SPLIT_BF16)):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         fwd, bwd = [], []
@@ -472,15 +550,24 @@ def adjoint_ratio(torch, reps=3):
             ev[3].record(D.stream)
             torch.cuda.synchronize()
             L.check_cells(a["status"])
+            del Kc, Kf
             if r:
                 fwd.append(ev[0].elapsed_time(ev[1]))
                 bwd.append(ev[2].elapsed_time(ev[3]))
         f, b = float(np.mean(fwd)), float(np.mean(bwd))
+        n = a["nsub"].cpu().numpy().astype(np.float64)
+        rt = 4 if prec == L.PREC_SPLIT_BF16 else 8
+        per_cell = (4 * rt * P + (1 + 3 * n) * (2 * rt * P + 16 * N) +
+                    3 * n * (4 * rt * P + 40 * N))
+        ach = float(per_cell.sum() / (b * 1e-3) / 1e9)
         out[name] = {"backward_ms": b, "forward_ms": f, "adjoint_over_forward": b / f,
-                     "accepted_substeps_per_cell": float(a["nsub"].float().mean())}
+                     "accepted_substeps_per_cell": float(n.mean()),
+                     "backward_roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                           "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}}
     out["note"] = ("same call both ways: the first call from the initial state; forward = rates "
                    "+ ADAPTIVE step; backward recomputes the rates, their derivative factors and "
-                   "the stage states, then runs the reverse sweep")
+                   "the stage states, then runs the reverse sweep; backward_roofline: the "
+                   "backward's algorithmic bytes (see bench.py adjoint_ratio) over its time")
     return out
 
 
@@ -565,8 +652,10 @@ def main():
     free, total = torch.cuda.mem_get_info()
     out["device_memory_used_gb"] = (total - free) / 1e9    # rates, workspaces, torch cache
     if not args.no_adjoint:
-        out["adjoint"] = adjoint_ratio(torch)
-        progress("adjoint timed")
+        out["adjoint"] = adjoint_ratio(torch, "disc64x32_n100_adj")
+        progress("adjoint timed on the 64x32 x 100 disc")
+        out["adjoint_on_bench_disc"] = adjoint_ratio(torch, args.config, reps=2)
+        progress(f"adjoint timed on {args.config}")
     if not args.no_cpu_baseline:
         progress("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(D.cfg, disc, args.cpu_sample_cells)

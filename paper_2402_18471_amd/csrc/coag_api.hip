@@ -425,9 +425,9 @@ static AdjWs adj_ws(int N, size_t P, long S, int L, int split, int gf32) {
     return w;
 }
 
-// cells per slab: all of them if their workspace fits the budget, else as
-// many whole 16-cell batches as fit (at least 4096 cells, a launch that still
-// fills the GPU)
+// cells per slab: all of them if their workspace fits the budget, else the
+// fewest slabs of whole 16-cell batches that fit it (at least 4096 cells, a
+// launch that still fills the GPU), all of about the same size
 constexpr size_t kAdjBudget = (size_t)8 << 30;
 
 static long adj_slab_cells(const coag_ctx *ctx, long C, int L, int split, int gf32) {
@@ -437,8 +437,10 @@ static long adj_slab_cells(const coag_ctx *ctx, long C, int L, int split, int gf
     }
     if (adj_ws(ctx->N, ctx->P, C, L, split, gf32).total <= kAdjBudget) return C;
     const size_t per16 = adj_ws(ctx->N, ctx->P, 16, L, split, gf32).total;
-    long s = (long)(kAdjBudget / per16) * kBatchCells;
-    if (s < 4096) s = 4096;
+    long smax = (long)(kAdjBudget / per16) * kBatchCells;
+    if (smax < 4096) smax = 4096;
+    const long nslab = (C + smax - 1) / smax;
+    const long s = ((C + nslab - 1) / nslab + kBatchCells - 1) / kBatchCells * kBatchCells;
     return s < C ? s : C;
 }
 
