@@ -245,16 +245,33 @@ int coag_step_noalloc(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, con
 
 /* Discrete adjoint of coag_rates + coag_step over a frozen step sequence
    (nsub[c] accepted steps of sizes h_log[c][:], as a REPLAY or FIXED call
-   reproduces them).  With J a scalar of the final state and g_out = dJ/drho_end:
-     g_in    [C][N] DEVICE out   dJ/drho at the start of the call
+   reproduces them): the derivative of the update of Sec. 5 (eqs. `smol`,
+   `ngain`, the loss term, the rates of eqs. `kernel`, `OCVrel`, `p_frag`)
+   through the Bogacki-Shampine stages.  With J a scalar of the final state and
+   g_out = dJ/drho_end:
+     g_in    [C][N] DEVICE out   dJ/drho at the start of the call (may be the
+                                 same array as g_out: in place)
      g_alpha [C]    DEVICE out   dJ/dalpha_c (through v_turb and Re)
      g_vfrag [C]    DEVICE out   dJ/dv_frag,c (through p_frag)
    Inputs rho_in [C][N], cells, v_dust, v_frag as for coag_rates; h_log
-   [C][log_stride], nsub [C] DEVICE.  The stage states are recomputed from
-   rho_in (by the batched step in REPLAY mode where that step applies) and
-   kept in the context's workspace for the reverse sweep.  prec: COAG_PREC_FP64 (the adjoint runs in FP64 only;
-   COAG_PREC_SPLIT_BF16 returns COAG_ENOTSUP).  Errors: COAG_EINVAL,
-   COAG_ENOTSUP, COAG_ENOMEM. */
+   [C][log_stride], nsub [C] DEVICE.  The rates and the stage states are
+   recomputed from rho_in and kept in the context's workspace for the reverse
+   sweep; nothing of size [C][P] is kept where the batched kernels apply (the
+   rate derivatives are folded into g_alpha, g_vfrag during the sweep), and the
+   workspace holds at most about 8 GiB, the cells being taken in equal slabs
+   (COAG_ADJ_SLAB_CELLS, read by coag_create, sets a smaller slab).
+   prec: COAG_PREC_FP64 (everything in FP64), or COAG_PREC_SPLIT_BF16 (the
+   adjoint of the split-precision step: FP32 rates and derivative factors, the
+   transposed gain sum on BF16 matrix cores from three-limb splits, the rest in
+   FP64; its mass renormalisation is taken as the identity).  Where the
+   batched kernels do not apply (the grid conditions of coag_step, or
+   COAG_STEP_KERNEL=cell) the FP64 adjoint runs one cell per workgroup with
+   [C][P] rate and rate-gradient buffers, and split precision returns
+   COAG_ENOTSUP.  A cell whose nsub is negative or above log_stride, or whose
+   replay fails (non-finite state), gets NaN in g_in, g_alpha and g_vfrag;
+   other cells are unaffected.  nsub = 0 gives g_in = g_out and zero g_alpha,
+   g_vfrag.  Errors: COAG_EINVAL (null pointer, C < 0, log_stride < 1, unknown
+   precision), COAG_ENOTSUP, COAG_ENOMEM. */
 int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coag_cells *cells,
                        const double *v_dust, const double *v_frag, const double *h_log,
                        int32_t log_stride, const int32_t *nsub, const double *g_out,
