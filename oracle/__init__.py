@@ -36,7 +36,8 @@ _ip = ct.POINTER(ct.c_int32)
 
 class _Grid(ct.Structure):
     _fields_ = [("N", ct.c_int32), ("split", ct.c_int32), ("m", _dp), ("m_edge", _dp),
-                ("s", _dp), ("rho_m", ct.c_double), ("eta", ct.c_double), ("chi", ct.c_double)]
+                ("s", _dp), ("rho_m", ct.c_double), ("eta", ct.c_double), ("chi", ct.c_double),
+                ("vertical", ct.c_int32)]
 
 
 class _Cells(ct.Structure):
@@ -115,7 +116,9 @@ def pair_index(i, j):
 class Grid:
     """Mass grid plus collision-outcome parameters (eta: fragment power law
     exponent, eq. ``fragdist``; chi: impactor excavation factor, eq.
-    ``fragrem``; split: two-bin split reading of eq. ``Cijk``)."""
+    ``fragrem``; split: two-bin split reading of eq. ``Cijk``; vertical: 1
+    for the vertically integrated kernel of Sec. 5.1, whose state is a column
+    density and whose cells give the midplane gas density)."""
     m: np.ndarray
     m_edge: np.ndarray
     s: np.ndarray
@@ -123,6 +126,7 @@ class Grid:
     eta: float = 11.0 / 6.0
     chi: float = 1.0
     split: int = SPLIT_MASS
+    vertical: int = 0
 
     @property
     def N(self) -> int:
@@ -135,7 +139,7 @@ class Grid:
     def _struct(self):
         self.m, self.m_edge, self.s = _f64(self.m), _f64(self.m_edge), _f64(self.s)
         return _Grid(self.N, self.split, _d(self.m), _d(self.m_edge), _d(self.s),
-                     self.rho_m, self.eta, self.chi)
+                     self.rho_m, self.eta, self.chi, int(self.vertical))
 
 
 def mass_grid(N, lo, hi, by_mass=False, rho_m=1.67):
@@ -147,9 +151,10 @@ def mass_grid(N, lo, hi, by_mass=False, rho_m=1.67):
     return m, me, s
 
 
-def make_grid(N, lo, hi, by_mass=False, rho_m=1.67, eta=11.0 / 6.0, chi=1.0, split=SPLIT_MASS):
+def make_grid(N, lo, hi, by_mass=False, rho_m=1.67, eta=11.0 / 6.0, chi=1.0, split=SPLIT_MASS,
+              vertical=0):
     m, me, s = mass_grid(N, lo, hi, by_mass, rho_m)
-    return Grid(m, me, s, rho_m, eta, chi, split)
+    return Grid(m, me, s, rho_m, eta, chi, split, vertical)
 
 
 def redistribution_dense(g: Grid):

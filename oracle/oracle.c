@@ -102,6 +102,7 @@ int ored_build(const oracle_grid_t *g, ored *r)
     memset(r, 0, sizeof(*r));
     r->N = N; r->P = P; r->m = g->m; r->m_edge = g->m_edge; r->s = g->s;
     r->rho_m = g->rho_m;
+    r->vertical = g->vertical;
     r->ci = malloc(P * sizeof(int)); r->cw0 = malloc(P * sizeof(double)); r->cw1 = malloc(P * sizeof(double));
     r->ri = malloc(P * sizeof(int)); r->rw0 = malloc(P * sizeof(double)); r->rw1 = malloc(P * sizeof(double));
     r->fl = malloc(P * sizeof(int)); r->fm = malloc(P * sizeof(double));
@@ -224,6 +225,7 @@ int oracle_rates(const oracle_grid_t *g, long C, const oracle_cells_t *c,
     memset(&r, 0, sizeof(r));
     r.N = g->N; r.P = (long)g->N * (g->N + 1) / 2;
     r.m = g->m; r.m_edge = g->m_edge; r.s = g->s; r.rho_m = g->rho_m;
+    r.vertical = g->vertical;
     const int N = r.N;
     const long P = r.P;
 #pragma omp parallel for schedule(dynamic, 4)
@@ -470,11 +472,28 @@ static void rates_cell_deriv(const ored *r, double Tgas, double rho_g, double c_
             double dx = v[3 * i + 0] - v[3 * j + 0];
             double dy = v[3 * i + 1] - v[3 * j + 1];
             double dz = v[3 * i + 2] - v[3 * j + 2];
+            /* vertically integrated kernel: h_k = H sqrt(alpha / (alpha + St_k))
+               has d ln h_k / d alpha = St_k / (2 alpha (alpha + St_k)) = e_k; the
+               settling speeds St_k Omega h_k and the overlap factor
+               G = (2 pi (h_i^2 + h_j^2))^(-1/2) move with alpha through h */
+            double G = 1.0, dlnG_da = 0.0, dvlam2_da = 0.0;
+            if (r->vertical) {
+                double h_i = H * sqrt(alpha / (alpha + St_i));
+                double h_j = H * sqrt(alpha / (alpha + St_j));
+                double e_i = St_i / (2.0 * alpha * (alpha + St_i));
+                double e_j = St_j / (2.0 * alpha * (alpha + St_j));
+                double vz_i = St_i * Omega * h_i, vz_j = St_j * Omega * h_j;
+                dz = vz_i - vz_j;
+                dvlam2_da = 2.0 * dz * (vz_i * e_i - vz_j * e_j);
+                double hh = h_i * h_i + h_j * h_j;
+                G = 1.0 / sqrt(2.0 * M_PI * hh);
+                dlnG_da = -(h_i * h_i * e_i + h_j * h_j * e_j) / hh;
+            }
             double vlam2 = dx * dx + dy * dy + dz * dz;
             double dv = sqrt(vbm2 + vturb2 + vlam2);
-            double ddv_da = dvturb2_da / (2.0 * dv);
+            double ddv_da = (dvturb2_da + dvlam2_da) / (2.0 * dv);
             double sig = M_PI * (s[i] + s[j]) * (s[i] + s[j]);
-            double K = sig * dv;
+            double K = sig * dv * G;
             double w = (i == j) ? 0.5 : 1.0;
 
             double pf, pc, dpf_dy;
@@ -498,9 +517,9 @@ static void rates_cell_deriv(const ored *r, double Tgas, double rho_g, double c_
             double dy_dvf = dv > 0 ? 3.0 * v_frag / (dv * dv) : 0.0;
             double dy_ddv = dv > 0 ? -2.0 * y / dv : 0.0;
             double dpf_ddv = dpf_dy * dy_ddv;
-            /* Kc = w sig dv pc, Kf = w sig dv pf, pc = 1 - pf */
-            dKf_da[p] = w * (sig * pf + K * dpf_ddv) * ddv_da;
-            dKc_da[p] = w * (sig * pc - K * dpf_ddv) * ddv_da;
+            /* Kc = w sig dv G pc, Kf = w sig dv G pf, pc = 1 - pf */
+            dKf_da[p] = w * (sig * G * pf + K * dpf_ddv) * ddv_da + w * K * pf * dlnG_da;
+            dKc_da[p] = w * (sig * G * pc - K * dpf_ddv) * ddv_da + w * K * pc * dlnG_da;
             dKf_dv[p] = w * K * dpf_dy * dy_dvf;
             dKc_dv[p] = -dKf_dv[p];
         }
@@ -677,6 +696,7 @@ int oracle_rates_deriv(const oracle_grid_t *g, long C, const oracle_cells_t *c,
     memset(&r, 0, sizeof(r));
     r.N = g->N; r.P = (long)g->N * (g->N + 1) / 2;
     r.m = g->m; r.m_edge = g->m_edge; r.s = g->s; r.rho_m = g->rho_m;
+    r.vertical = g->vertical;
     const long P = r.P;
     for (long q = 0; q < C; ++q)
         rates_cell_deriv(&r, c->T[q], c->rho_g[q], c->c_s[q], c->Omega[q], c->H[q],

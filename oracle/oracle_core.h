@@ -31,6 +31,7 @@ typedef struct {
     int32_t split;                    /* ORACLE_SPLIT_* */
     const double *m, *m_edge, *s;     /* [N], [N+1], [N] */
     double rho_m, eta, chi;
+    int32_t vertical;                 /* 1: vertically integrated kernel (Sec. 5.1) */
 } oracle_grid_t;
 
 /* Per-cell gas state, one value per cell for each array. */
@@ -50,6 +51,7 @@ typedef struct {
     long P;
     const double *m, *m_edge, *s;
     double rho_m;
+    int vertical;                     /* vertically integrated kernel */
     int *ci;  double *cw0, *cw1;      /* coagulation: lower bin, mass into ci, ci+1 */
     int *ri;  double *rw0, *rw1;      /* remnant:     lower bin, mass into ri, ri+1 */
     int *fl;  double *fm;             /* fragments:   top bin l, total fragment mass */

@@ -10,6 +10,9 @@ Disc shape follows the paper's transition-disc test (Sec. 7, table `params`):
 Sigma_g = Sigma_0 R_au^-1 exp[-(5/R_au)^10], Sigma_0 = 250 g cm^-2, M_* = 1 M_sun,
 mu = 2.4; vertically isothermal T = 150 K (R/au)^-1/2; Gaussian rho_g(Z) with
 H/R = 0.05; MRN initial dust (n(s) ~ s^-3.5) up to 1 micron at dust-to-gas 0.01.
+Columns for the vertically integrated kernel follow the paper's single-radius
+coagulation test (Sec. 5.1): R = 20 au, T = 36 K, mu = 2.4, alpha = 1e-3,
+v_frag = 1 m/s, 200 species.
 No public dataset is involved; every random draw is seeded.
 """
 from __future__ import annotations
@@ -166,3 +169,80 @@ def subset_cells(disc, idx):
     return dict(cells=cells, v_dust=np.ascontiguousarray(disc["v_dust"][idx]),
                 v_frag=np.ascontiguousarray(disc["v_frag"][idx]),
                 rho=np.ascontiguousarray(disc["rho"][idx]), dt=disc["dt"])
+
+
+# ---------------------------------------------------------------------------
+# Vertically integrated columns (surface densities).
+# ---------------------------------------------------------------------------
+@dataclass
+class ColumnConfig:
+    """Columns of a disc at n_r radii, each evolved as one cell of the
+    vertically integrated kernel: the state is the dust surface density per
+    bin, the cell's rho_g the midplane gas density Sigma_g / (sqrt(2 pi) H)
+    with H = c_s / Omega.  T = T_ref (R / r_ref)^-1/2; Sigma_g follows the
+    disc above, Sigma_0 R_au^-1 exp[-(5/R_au)^10]."""
+    name: str
+    n_r: int
+    n_bins: int
+    s_min: float                 # cm
+    s_max: float                 # cm
+    r_in_au: float = 20.0
+    r_out_au: float = 20.0
+    T_ref: float = 36.0          # K at r_ref_au
+    r_ref_au: float = 20.0
+    alpha: float = 1e-3
+    v_frag: float = 100.0        # cm/s
+    drift: bool = False          # radial drift and azimuthal lag in v_dust (else zero)
+    steps: int = 200
+    dt: float = 100.0 * YEAR     # s per coagulation call
+    rho_m: float = 1.67
+    mu: float = 2.4
+    sigma0: float = 250.0
+    dust_to_gas: float = 0.01
+    s_mrn_max: float = 1.0e-4    # cm
+
+    @property
+    def n_cells(self) -> int:
+        return self.n_r
+
+
+COLUMNS = {
+    # the paper's single-radius test shape: one column at 20 au, 200 species
+    # (0.1 um - 1 m), dynamics off
+    "col0d_n200": ColumnConfig("col0d_n200", 1, 200, 1e-5, 100.0),
+    # 4096 columns, 5 - 100 au, with radial drift and azimuthal lag
+    "col4096_n200": ColumnConfig("col4096_n200", 4096, 200, 1e-5, 100.0, 5.0, 100.0, drift=True),
+}
+
+
+def make_columns(cfg: ColumnConfig, s):
+    """Everything one vertically integrated coagulation call needs, for bin
+    radii s [N]: per-column gas state (rho_g the midplane density), v_dust
+    [C][N][3] (its vertical component unused by that kernel), v_frag, and the
+    MRN start as surface densities [C][N] in g cm^-2."""
+    r_au = np.geomspace(cfg.r_in_au, cfg.r_out_au, cfg.n_r)
+    R = r_au * AU
+    T = cfg.T_ref * (r_au / cfg.r_ref_au) ** -0.5
+    c_s = np.sqrt(K_B * T / (cfg.mu * M_H))
+    Omega = np.sqrt(G_GRAV * M_SUN / R ** 3)
+    H = c_s / Omega
+    sigma_g = cfg.sigma0 / r_au * np.exp(-(5.0 / r_au) ** 10)
+    rho_g = sigma_g / (np.sqrt(2.0 * np.pi) * H)
+    v_th = np.sqrt(8.0 / np.pi) * c_s
+    nu_mol = 0.5 * v_th * cfg.mu * M_H / (rho_g * SIGMA_H2)
+    alpha = np.full(cfg.n_r, float(cfg.alpha))
+    f = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    cells = dict(R=f(R), Z=np.zeros(cfg.n_r), Sigma_g=f(sigma_g), T=f(T), rho_g=f(rho_g),
+                 c_s=f(c_s), Omega=f(Omega), H=f(H), nu_mol=f(nu_mol), alpha=f(alpha))
+    s = np.asarray(s, dtype=np.float64)
+    if cfg.drift:
+        v = make_dust_velocities(cfg, cells, s)
+    else:
+        v = np.zeros((cfg.n_r, s.shape[0], 3))
+    shape = np.where(s <= cfg.s_mrn_max * (1 + 1e-12), np.sqrt(s), 0.0)
+    if not shape.any():
+        shape[0] = 1.0
+    shape = shape / shape.sum()
+    rho = np.ascontiguousarray(cfg.dust_to_gas * sigma_g[:, None] * shape[None, :])
+    return dict(cells=cells, v_dust=v, v_frag=np.full(cfg.n_r, float(cfg.v_frag)), rho=rho,
+                dt=cfg.dt)
