@@ -88,7 +88,19 @@ enum { COAG_RATES_CP64 = 0, COAG_RATES_BLK32 = 1, COAG_RATES_BLK64 = 2 };
    (bin edges, used by the fragment distribution eq. `Nijk`); s = grain radius
    of each bin (cm).  rho_m: grain material density; eta: fragment power law
    n(m) ~ m^-eta (eq. `fragdist`, eta != 2); chi: excavated mass in units of
-   the impactor mass (eq. `fragrem`, chi > 0); split: COAG_SPLIT_*. */
+   the impactor mass (eq. `fragrem`, chi > 0); split: COAG_SPLIT_*.
+   vertical: 0 for the volume kernel (states are mass densities per bin,
+   g cm^-3, each cell a point of the (R, Z) grid); 1 for the vertically
+   integrated kernel of the paper's single-radius test (Sec. 5.1): states
+   are surface densities per bin (g cm^-2), each cell a column whose rho_g is
+   the midplane gas density and whose grains have Gaussian vertical profiles
+   of scale height h_k = H sqrt(alpha / (alpha + St_k)); the pair rate is the
+   volume rate integrated over height, K / sqrt(2 pi (h_i^2 + h_j^2)), and the
+   vertical relative velocity the difference of the settling speeds
+   St_k Omega h_k (the vertical components of v_dust are not used).  The
+   vertical form needs alpha > 0 in every cell (else the rates are not
+   finite).  Chosen per context: every rate, step and adjoint call of the
+   context takes it. */
 typedef struct {
     int32_t n_bins;           /* N, 2 <= N <= 1023 */
     int32_t split;
@@ -96,6 +108,7 @@ typedef struct {
     const double *m_edge;     /* [N+1] HOST */
     const double *s;          /* [N]   HOST */
     double rho_m, eta, chi;
+    int32_t vertical;         /* 0 volume kernel, 1 vertically integrated */
 } coag_grid;
 
 /* Per-cell gas state, each a DEVICE array [C]: temperature T (K), gas density

@@ -28,7 +28,8 @@ _vp = ct.c_void_p
 
 class Grid(ct.Structure):
     _fields_ = [("n_bins", ct.c_int32), ("split", ct.c_int32), ("m", _dp), ("m_edge", _dp),
-                ("s", _dp), ("rho_m", ct.c_double), ("eta", ct.c_double), ("chi", ct.c_double)]
+                ("s", _dp), ("rho_m", ct.c_double), ("eta", ct.c_double), ("chi", ct.c_double),
+                ("vertical", ct.c_int32)]
 
 
 class Cells(ct.Structure):

@@ -49,17 +49,22 @@ def _stream():
 
 
 class CoagContext:
-    """coag_create / coag_destroy around one mass grid on the current device."""
+    """coag_create / coag_destroy around one mass grid on the current device.
+    vertical=True selects the vertically integrated kernel (states are
+    surface densities, cells are columns; see coag_grid in include/coag.h)."""
 
-    def __init__(self, m, m_edge, s, rho_m=1.67, eta=11.0 / 6.0, chi=1.0, split=L.SPLIT_MASS):
+    def __init__(self, m, m_edge, s, rho_m=1.67, eta=11.0 / 6.0, chi=1.0, split=L.SPLIT_MASS,
+                 vertical=False):
         self.m = np.ascontiguousarray(m, dtype=np.float64)
         self.m_edge = np.ascontiguousarray(m_edge, dtype=np.float64)
         self.s = np.ascontiguousarray(s, dtype=np.float64)
         self.N = int(self.m.shape[0])
         self.P = self.N * (self.N + 1) // 2
         self.rho_m, self.eta, self.chi, self.split = rho_m, eta, chi, split
+        self.vertical = bool(vertical)
         dp = lambda a: a.ctypes.data_as(L._dp)
-        g = L.Grid(self.N, split, dp(self.m), dp(self.m_edge), dp(self.s), rho_m, eta, chi)
+        g = L.Grid(self.N, split, dp(self.m), dp(self.m_edge), dp(self.s), rho_m, eta, chi,
+                   int(self.vertical))
         h = ct.c_void_p()
         self._lib = L.load()
         L.check(self._lib.coag_create(ct.byref(g), ct.byref(h)))

@@ -26,7 +26,9 @@
 // derivatives, which follow from the rates and two per-pair factors Z, X
 // (pair_rate_derivs) that a pre-pass writes per call next to the rates:
 //   dJ/dalpha  += Z (a ga + D),   dJ/dv_frag += -D / v_frag,
-//   D = a X Kf (sf - sc).
+//   D = a X Kf (sf - sc);
+// the vertically integrated kernel adds W a ga to dJ/dalpha, W = d ln G /
+// d alpha of its overlap factor G (a third per-pair factor).
 //
 // The reverse sweep of one BS3 step of size h from the adjoint state lambda
 // (the transposed stage recurrences):
@@ -52,38 +54,48 @@ namespace {
 using namespace bc;
 
 // ---------------------------------------------------------------------------
-// Rate-derivative factors Z, X in the 16-cell-blocked layout: 16 cells per workgroup of
-// 1024 threads, thread t on cell t % 16 and pairs t / 16 + 64 k (the 16 cells
-// of a pair leave as one run).  Per-grain St and velocity of the 16 cells in
-// LDS as [bin][value][cell] (TAB = 4), or St alone (TAB = 1, velocities from
-// v_dust) where that would not fit.
+// Rate-derivative factors Z, X (and W for the vertically integrated kernel,
+// VI) in the 16-cell-blocked layout: 16 cells per workgroup of 1024 threads,
+// thread t on cell t % 16 and pairs t / 16 + 64 k (the 16 cells of a pair
+// leave as one run).  Per-grain St and velocity of the 16 cells in LDS as
+// [bin][value][cell] (TAB = 4), or St alone (TAB = 1, velocities from v_dust)
+// where that would not fit; VI adds h^2 and e = d ln h / d alpha per grain,
+// and its vertical velocity is the settling speed.
 // ---------------------------------------------------------------------------
-template <int TAB>
-size_t derivs_lds_bytes(int N) { return (size_t)(16 * TAB + 1) * N * sizeof(double); }
+template <int TAB, bool VI>
+size_t derivs_lds_bytes(int N) {
+    return (size_t)(16 * (TAB + (VI ? 2 : 0)) + 1) * N * sizeof(double);
+}
 
-template <int TAB, typename GT>
+template <int TAB, bool VI, typename GT>
 __global__ __launch_bounds__(1024) void k_rate_derivs_blk(Tables T, CellArrays cells,
                                                           const double *__restrict__ v_dust,
                                                           const double *__restrict__ v_frag,
                                                           GT *__restrict__ Zo,
-                                                          GT *__restrict__ Xo, long C) {
+                                                          GT *__restrict__ Xo,
+                                                          GT *__restrict__ Wo, long C) {
     extern __shared__ double lds[];
+    constexpr int TW = TAB + (VI ? 2 : 0);             // values per grain; h^2, e last
     const int N = T.N, P = T.P;
     const long cell0 = (long)blockIdx.x * 16;
-    double *tb = lds, *imv = lds + 16 * TAB * N;
-    auto tab = [&](int v, int k, int cl) -> double & { return tb[(k * TAB + v) * 16 + cl]; };
+    double *tb = lds, *imv = lds + 16 * TW * N;
+    auto tab = [&](int v, int k, int cl) -> double & { return tb[(k * TW + v) * 16 + cl]; };
     for (int t = threadIdx.x; t < 16 * N; t += 1024) {
         const int cl = t & 15, k = t >> 4;
         const long c = cell0 + cl;
-        double st = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
+        double st = 0.0, vx = 0.0, vy = 0.0, vz = 0.0, h2 = 0.0, e = 0.0;
         if (c < C) {
             const CellRate r = cell_rate(cells, v_frag, c);
             st = T.rho_m * T.s[k] / r.rg_vth * r.Om;
+            if (VI) {
+                h2 = grain_h2(r, st);
+                e = vertical_e(r, st);
+            }
             if (TAB == 4) {
                 const double *v = v_dust + (c * N + k) * 3;
                 vx = v[0];
                 vy = v[1];
-                vz = v[2];
+                vz = VI ? settle_speed(r, st, h2) : v[2];
             }
         }
         tab(0, k, cl) = st;
@@ -91,6 +103,10 @@ __global__ __launch_bounds__(1024) void k_rate_derivs_blk(Tables T, CellArrays c
             tab(1, k, cl) = vx;
             tab(2, k, cl) = vy;
             tab(3, k, cl) = vz;
+        }
+        if (VI) {
+            tab(TAB, k, cl) = h2;
+            tab(TAB + 1, k, cl) = e;
         }
     }
     for (int k = threadIdx.x; k < N; k += 1024) imv[k] = 1.0 / T.m[k];
@@ -104,20 +120,32 @@ __global__ __launch_bounds__(1024) void k_rate_derivs_blk(Tables T, CellArrays c
     const CellRate r = cell_rate(cells, v_frag, cc);
     const double alpha = cells.alpha[cc], cs = cells.c_s[cc], cs2 = cs * cs;
     const double *vc = v_dust + cc * N * 3;
-    auto vel = [&](int k, int d) { return TAB == 4 ? tab(1 + d, k, cl) : vc[3 * k + d]; };
+    auto vel = [&](int k, int d) {
+        if (TAB == 4) return tab(1 + d, k, cl);
+        if (VI && d == 2) return settle_speed(r, tab(0, k, cl), tab(TAB, k, cl));
+        return vc[3 * k + d];
+    };
     GT *oz = Zo + cell0 * P + cl, *ox = Xo + cell0 * P + cl;
     for (int p = p0 + slot; p < p1; p += 64) {
         RateDerivs d{0.0, 0.0};
+        double w = 0.0;
         if (live) {
             const uint32_t ij = T.pij[p];
             const int i = pair_i(ij), j = pair_j(ij);
-            const double dx = vel(i, 0) - vel(j, 0), dy = vel(i, 1) - vel(j, 1),
-                         dz = vel(i, 2) - vel(j, 2);
+            const double vzi = vel(i, 2), vzj = vel(j, 2);
+            const double dx = vel(i, 0) - vel(j, 0), dy = vel(i, 1) - vel(j, 1), dz = vzi - vzj;
+            double dvlam2_da = 0.0;
+            if (VI) {
+                const double ei = tab(TAB + 1, i, cl), ej = tab(TAB + 1, j, cl);
+                dvlam2_da = 2.0 * dz * (vzi * ei - vzj * ej);
+                w = vertical_w(tab(TAB, i, cl), ei, tab(TAB, j, cl), ej);
+            }
             d = pair_rate_derivs(r, alpha, cs2, tab(0, i, cl), tab(0, j, cl), imv[i], imv[j],
-                                 dx * dx + dy * dy + dz * dz);
+                                 dx * dx + dy * dy + dz * dz, dvlam2_da);
         }
         oz[(long)p * 16] = (GT)d.Z;
         ox[(long)p * 16] = (GT)d.X;
+        if (VI) Wo[cell0 * P + cl + (long)p * 16] = (GT)w;
     }
 }
 
@@ -160,7 +188,7 @@ __host__ __device__ inline AdjLds adj_lds_layout(int N, int prec) {
 constexpr int kRingA = 2;
 static_assert(kRingA % 2 == 0, "the D operands alternate between two register sets by chunk parity");
 
-template <int PREC, typename RT, typename GT>
+template <int PREC, typename RT, typename GT, bool VI>
 __global__ __launch_bounds__(kBBlock) void k_adj_batch(Tables T, BatchTables B, AdjBatchArgs a,
                                                        long C) {
     extern __shared__ double lds_d[];
@@ -346,8 +374,9 @@ __global__ __launch_bounds__(kBBlock) void k_adj_batch(Tables T, BatchTables B, 
         const long kbase = cell0 * P;
         const RT *Kc = (const RT *)a.Kc + kbase, *Kf = (const RT *)a.Kf + kbase;
         const GT *Zp = (const GT *)a.Z + kbase, *Xp = (const GT *)a.X + kbase;
+        const GT *Wp = VI ? (const GT *)a.W + kbase : nullptr;
         RT rc[kRingA][4], rf[kRingA][4];
-        GT ez[kRingA][4], ex[kRingA][4];
+        GT ez[kRingA][4], ex[kRingA][4], ew[kRingA][VI ? 4 : 1];
         auto load_k = [&](int i, int q, int u) {
             const int prow = i * (i + 1) / 2;
 #pragma unroll
@@ -358,6 +387,7 @@ __global__ __launch_bounds__(kBBlock) void k_adj_batch(Tables T, BatchTables B, 
                 rf[u][r] = Kf[o];
                 ez[u][r] = Zp[o];
                 ex[u][r] = Xp[o];
+                if (VI) ew[u][VI ? r : 0] = Wp[o];
             }
         };
         int rleft = c1 - c0;
@@ -459,6 +489,7 @@ __global__ __launch_bounds__(kBBlock) void k_adj_batch(Tables T, BatchTables B, 
                 col[r] += ni * ga;
                 const double D = aa * (double)ex[u][r] * kf * (sf - sc);
                 gacc_a += (double)ez[u][r] * (aa * ga + D);
+                if (VI) gacc_a += (double)ew[u][VI ? r : 0] * (aa * ga);
                 gacc_v += D;
             }
             atomicAdd(&gnrow[i], rows);
@@ -529,23 +560,33 @@ bool adj_batch_available(const Tables &T, const BatchTables &B) {
 
 hipError_t launch_rate_derivs_blocked(const Tables &T, long C, const CellArrays &cells,
                                       const double *v_dust, const double *v_frag, int f32,
-                                      void *Z, void *X, hipStream_t st) {
+                                      void *Z, void *X, void *W, hipStream_t st) {
     if (C == 0) return hipSuccess;
+    const bool vi = T.vertical != 0;
+    if (vi && !W) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((C + 15) / 16);
     const unsigned slices = blocks >= 512 ? 1u : min(8u, (512u + blocks - 1) / blocks);
-    const bool tab4 = derivs_lds_bytes<4>(T.N) <= 160 * 1024;
-#define DERIVS(TAB, GT)                                                                          \
-    {                                                                                            \
-        const size_t bytes = derivs_lds_bytes<TAB>(T.N);                                         \
-        if (hipError_t e = allow_lds_a(k_rate_derivs_blk<TAB, GT>, bytes)) return e;             \
-        hipLaunchKernelGGL((k_rate_derivs_blk<TAB, GT>), dim3(blocks, slices), dim3(1024), bytes, \
-                           st, T, cells, v_dust, v_frag, (GT *)Z, (GT *)X,                       \
-                           C);                                                                   \
+    const bool tab4 = (vi ? derivs_lds_bytes<4, true>(T.N) : derivs_lds_bytes<4, false>(T.N)) <=
+                      160 * 1024;
+#define DERIVS(TAB, VI, GT)                                                                     \
+    {                                                                                           \
+        const size_t bytes = derivs_lds_bytes<TAB, VI>(T.N);                                    \
+        if (hipError_t e = allow_lds_a(k_rate_derivs_blk<TAB, VI, GT>, bytes)) return e;        \
+        hipLaunchKernelGGL((k_rate_derivs_blk<TAB, VI, GT>), dim3(blocks, slices), dim3(1024),  \
+                           bytes, st, T, cells, v_dust, v_frag, (GT *)Z, (GT *)X, (GT *)W, C);  \
     }
-    if (f32) {
-        if (tab4) DERIVS(4, float) else DERIVS(1, float)
+    if (!vi) {
+        if (f32) {
+            if (tab4) DERIVS(4, false, float) else DERIVS(1, false, float)
+        } else {
+            if (tab4) DERIVS(4, false, double) else DERIVS(1, false, double)
+        }
     } else {
-        if (tab4) DERIVS(4, double) else DERIVS(1, double)
+        if (f32) {
+            if (tab4) DERIVS(4, true, float) else DERIVS(1, true, float)
+        } else {
+            if (tab4) DERIVS(4, true, double) else DERIVS(1, true, double)
+        }
     }
 #undef DERIVS
     return hipGetLastError();
@@ -557,14 +598,22 @@ hipError_t launch_adjoint_batch(const Tables &T, const BatchTables &B, long C,
     if (!adj_batch_available(T, B)) return hipErrorNotSupported;
     const size_t bytes = adj_lds_layout(T.N, prec).total;
     const dim3 grid((unsigned)((C + kBC - 1) / kBC)), block(kBBlock);
-#define LAUNCH(PR, RT, GT)                                                                  \
-    do {                                                                                    \
-        if (hipError_t e = allow_lds_a(k_adj_batch<PR, RT, GT>, bytes)) return e;          \
-        hipLaunchKernelGGL((k_adj_batch<PR, RT, GT>), grid, block, bytes, st, T, B, a, C); \
+    const bool vi = T.vertical != 0;
+    if (vi && !a.W) return hipErrorInvalidValue;
+#define LAUNCH(PR, RT, GT, VI)                                                                  \
+    do {                                                                                        \
+        if (hipError_t e = allow_lds_a(k_adj_batch<PR, RT, GT, VI>, bytes)) return e;          \
+        hipLaunchKernelGGL((k_adj_batch<PR, RT, GT, VI>), grid, block, bytes, st, T, B, a, C); \
     } while (0)
-    if (prec == 0) LAUNCH(0, double, double);
-    else if (gf32) LAUNCH(1, float, float);
-    else LAUNCH(1, float, double);
+    if (!vi) {
+        if (prec == 0) LAUNCH(0, double, double, false);
+        else if (gf32) LAUNCH(1, float, float, false);
+        else LAUNCH(1, float, double, false);
+    } else {
+        if (prec == 0) LAUNCH(0, double, double, true);
+        else if (gf32) LAUNCH(1, float, float, true);
+        else LAUNCH(1, float, double, true);
+    }
 #undef LAUNCH
     return hipGetLastError();
 }

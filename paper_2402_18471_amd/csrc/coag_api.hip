@@ -133,6 +133,9 @@ int coag_create(const coag_grid *g, coag_ctx **out) {
     if (!(g->rho_m > 0.0)) return fail(nullptr, COAG_EINVAL, "coag_create: rho_m must be > 0");
     if (g->split != COAG_SPLIT_MASS && g->split != COAG_SPLIT_NUMBER)
         return fail(nullptr, COAG_EINVAL, "coag_create: unknown split %d", g->split);
+    if (g->vertical != 0 && g->vertical != 1)
+        return fail(nullptr, COAG_EINVAL, "coag_create: vertical must be 0 or 1, not %d",
+                    g->vertical);
 
     coag_ctx *ctx = new coag_ctx();
     if (hipGetDevice(&ctx->device) != hipSuccess) {
@@ -202,6 +205,7 @@ int coag_create(const coag_grid *g, coag_ctx **out) {
     T.rdiag = (int *)(b + o_rd);
     T.chi = g->chi;
     T.split = g->split;
+    T.vertical = g->vertical;
     double *me = (double *)(b + o_me);
     int rc = COAG_OK;
     hipError_t e = hipMemcpy((void *)T.m, g->m, 8 * N, hipMemcpyHostToDevice);
@@ -402,10 +406,10 @@ int coag_step_noalloc(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, con
 // replay's step starts Ys and stage states Zs, the replay's state, slopes and
 // status, and v3.  (Zf, Xf: the rate-derivative factors Z, X.)
 struct AdjWs {
-    size_t Kc, Kf, Zf, Xf, Ys, Zs, y, slopes, status, v3, total;
+    size_t Kc, Kf, Zf, Xf, Wf, Ys, Zs, y, slopes, status, v3, total;
 };
 
-static AdjWs adj_ws(int N, size_t P, long S, int L, int split, int gf32) {
+static AdjWs adj_ws(int N, size_t P, long S, int L, int split, int gf32, bool vertical) {
     const size_t Sb = ((size_t)S + kBatchCells - 1) / kBatchCells * kBatchCells;
     const size_t rt = split ? 4 : 8, gt = gf32 ? 4 : 8;
     AdjWs w;
@@ -415,6 +419,7 @@ static AdjWs adj_ws(int N, size_t P, long S, int L, int split, int gf32) {
     w.Kf = take(rt * P * Sb);
     w.Zf = take(gt * P * Sb);
     w.Xf = take(gt * P * Sb);
+    w.Wf = vertical ? take(gt * P * Sb) : 0;
     w.Ys = take(8 * (size_t)N * (size_t)(L + 1) * (size_t)S);
     w.Zs = take(8 * (size_t)N * 2 * (size_t)L * (size_t)S);
     w.y = take(8 * (size_t)N * (size_t)S);
@@ -435,8 +440,9 @@ static long adj_slab_cells(const coag_ctx *ctx, long C, int L, int split, int gf
         const long s = (ctx->adj_slab + kBatchCells - 1) / kBatchCells * kBatchCells;
         return s < C ? s : C;
     }
-    if (adj_ws(ctx->N, ctx->P, C, L, split, gf32).total <= kAdjBudget) return C;
-    const size_t per16 = adj_ws(ctx->N, ctx->P, 16, L, split, gf32).total;
+    const bool vt = ctx->T.vertical != 0;
+    if (adj_ws(ctx->N, ctx->P, C, L, split, gf32, vt).total <= kAdjBudget) return C;
+    const size_t per16 = adj_ws(ctx->N, ctx->P, 16, L, split, gf32, vt).total;
     long smax = (long)(kAdjBudget / per16) * kBatchCells;
     if (smax < 4096) smax = 4096;
     const long nslab = (C + smax - 1) / smax;
@@ -462,6 +468,11 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
                     "coag_step_backward: the split-BF16 adjoint needs the batched kernels "
                     "(N >= 16 bins whose products of each row fit a 16-bin window, and the "
                     "state of 16 cells within the LDS of one workgroup)");
+    if (ctx->T.vertical && !batched)
+        return fail(ctx, COAG_ENOTSUP,
+                    "coag_step_backward: the adjoint of the vertically integrated kernel "
+                    "needs the batched kernels (the per-cell adjoint has the volume kernel's "
+                    "rate derivatives only)");
     if (C == 0) return COAG_OK;
     if (int r = check_cells(ctx, cells)) return r;
     if (!rho_in || !v_dust || !v_frag || !h_log || !nsub || !g_out || !g_in || !g_alpha || !g_vfrag)
@@ -476,7 +487,7 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
         const int gf32 = split ? 1 : 0;
         const int L = log_stride;
         const long S = adj_slab_cells(ctx, C, L, split, gf32);
-        const AdjWs w = adj_ws(ctx->N, P, S, L, split, gf32);
+        const AdjWs w = adj_ws(ctx->N, P, S, L, split, gf32, ctx->T.vertical != 0);
         if (int r = ensure_ws(ctx, w.total)) return r;
         char *b = (char *)ctx->ws;
         for (long s0 = 0; s0 < C; s0 += S) {
@@ -487,7 +498,8 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
             HIP_TRY(ctx, launch_rates_blocked(ctx->T, Cs, cs, vd, vf, split ? 1 : 0, b + w.Kc,
                                               b + w.Kf, st));
             HIP_TRY(ctx, launch_rate_derivs_blocked(ctx->T, Cs, cs, vd, vf, gf32, b + w.Zf,
-                                                    b + w.Xf, st));
+                                                    b + w.Xf, ctx->T.vertical ? b + w.Wf : nullptr,
+                                                    st));
             double *y = (double *)(b + w.y);
             HIP_TRY(ctx, hipMemcpyAsync(y, rho_in + (size_t)s0 * N, 8 * N * (size_t)Cs,
                                         hipMemcpyDeviceToDevice, st));
@@ -515,6 +527,7 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
             aa.Kf = b + w.Kf;
             aa.Z = b + w.Zf;
             aa.X = b + w.Xf;
+            aa.W = ctx->T.vertical ? b + w.Wf : nullptr;
             aa.v_frag = vf;
             aa.Ys = sa.Ys;
             aa.Zs = sa.Zs;

@@ -64,6 +64,7 @@ size_t batch_ws_bytes(int N, long C, int prec, int layout);
 struct AdjBatchArgs {
     const void *Kc, *Kf;                 // [ceil(C/16)][P][16] RT
     const void *Z, *X;                   // [ceil(C/16)][P][16] GT
+    const void *W;                       // the same, vertically integrated kernel only
     const double *v_frag;                // [C]
     const double *Ys, *Zs;
     const double *h_log;
@@ -79,11 +80,12 @@ struct AdjBatchArgs {
 // whether the batched adjoint runs for this context (the batched step does,
 // and its LDS fits)
 bool adj_batch_available(const Tables &T, const BatchTables &B);
-// the rate-derivative factors Z, X (pair_rate_derivs) in the 16-cell-blocked
-// layout, double (f32 = 0) or float (f32 = 1)
+// the rate-derivative factors Z, X (pair_rate_derivs), and W of the
+// vertically integrated kernel (T.vertical; W unused otherwise), in the
+// 16-cell-blocked layout, double (f32 = 0) or float (f32 = 1)
 hipError_t launch_rate_derivs_blocked(const Tables &T, long C, const CellArrays &cells,
                                       const double *v_dust, const double *v_frag, int f32,
-                                      void *Z, void *X, hipStream_t st);
+                                      void *Z, void *X, void *W, hipStream_t st);
 // prec 0: FP64 rates and derivatives, FP64 matrix cores; prec 1: FP32 rates,
 // derivatives of type given by gf32, split-BF16 matrix products
 hipError_t launch_adjoint_batch(const Tables &T, const BatchTables &B, long C,

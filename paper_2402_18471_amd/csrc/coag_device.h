@@ -39,6 +39,7 @@ struct Tables {
                            //     pair (i, j) of row i, the largest such j (0 if none)
     double chi;            // excavated mass / impactor mass
     int split;             // 0 MASS, 1 NUMBER
+    int vertical;          // 1: vertically integrated kernel (column densities)
 };
 
 __device__ __forceinline__ int pair_i(uint32_t v) { return v & 1023u; }

@@ -144,8 +144,9 @@ __global__ __launch_bounds__(kRatesBlock) void k_rates(Tables T, CellArrays cell
     const long c = blockIdx.x;
     double *St = lds, *A = lds + N, *Bt = lds + 2 * N, *Ct = lds + 3 * N, *Sv = lds + 4 * N,
            *vx = lds + 5 * N, *vy = lds + 6 * N, *vz = lds + 7 * N, *im = lds + 8 * N,
-           *sv = lds + 9 * N;
+           *sv = lds + 9 * N, *h2 = lds + 10 * N;
     const CellRate r = cell_rate(cells, v_frag, c);
+    const bool vert = T.vertical != 0;
     for (int k = threadIdx.x; k < N; k += kRatesBlock) {
         Grain g;
         grain_terms(r, T.rho_m, T.s[k], g);
@@ -159,7 +160,13 @@ __global__ __launch_bounds__(kRatesBlock) void k_rates(Tables T, CellArrays cell
         const double *v = v_dust + (c * N + k) * 3;
         vx[k] = v[0];
         vy[k] = v[1];
-        vz[k] = v[2];
+        if (vert) {
+            h2[k] = grain_h2(r, g.st);
+            vz[k] = settle_speed(r, g.st, h2[k]);
+        } else {
+            h2[k] = 0.0;
+            vz[k] = v[2];
+        }
     }
     __syncthreads();
     auto grain = [&](int k) {
@@ -173,6 +180,7 @@ __global__ __launch_bounds__(kRatesBlock) void k_rates(Tables T, CellArrays cell
         g.vz = vz[k];
         g.im = im[k];
         g.s = sv[k];
+        g.h2 = h2[k];
         return g;
     };
     double *kc = Kc + c * P, *kf = Kf + c * P;
@@ -184,7 +192,7 @@ __global__ __launch_bounds__(kRatesBlock) void k_rates(Tables T, CellArrays cell
         Grain gi = grain(i);
         heavier_terms(r, gi, Sv[i]);
         double c64, f64;
-        pair_rates(r, gi, grain(j), i == j, c64, f64);
+        pair_rates(r, gi, grain(j), i == j, vert, c64, f64);
         kc[p] = c64;
         kf[p] = f64;
     }
@@ -192,7 +200,7 @@ __global__ __launch_bounds__(kRatesBlock) void k_rates(Tables T, CellArrays cell
 
 // Pair rates in the 16-cell-blocked layout, 16 cells per workgroup of 1024
 // threads (rates_block); blockIdx.y takes slice y of gridDim.y of the pairs.
-template <int TAB, typename OT>
+template <int TAB, bool VI, typename OT>
 __global__ __launch_bounds__(1024) void k_rates_blk(Tables T, CellArrays cells,
                                                     const double *__restrict__ v_dust,
                                                     const double *__restrict__ v_frag,
@@ -202,8 +210,8 @@ __global__ __launch_bounds__(1024) void k_rates_blk(Tables T, CellArrays cells,
     const int P = T.P;
     const int p0 = (int)((long)P * blockIdx.y / gridDim.y);
     const int p1 = (int)((long)P * (blockIdx.y + 1) / gridDim.y);
-    rates_block<TAB, 1024>(T, cells, v_dust, v_frag, Kc, Kf, C, (long)blockIdx.x * 16, p0, p1,
-                           lds);
+    rates_block<TAB, VI, 1024>(T, cells, v_dust, v_frag, Kc, Kf, C, (long)blockIdx.x * 16, p0,
+                               p1, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -547,7 +555,7 @@ hipError_t launch_build(int N, const double *m, const double *me, double eta, do
 hipError_t launch_rates(const Tables &T, long C, const CellArrays &cells, const double *v_dust,
                         const double *v_frag, double *Kc, double *Kf, hipStream_t st) {
     if (C == 0) return hipSuccess;
-    const size_t bytes = lds_bytes(10 * T.N);
+    const size_t bytes = lds_bytes(11 * T.N);
     if (hipError_t e = allow_lds(k_rates, bytes)) return e;
     hipLaunchKernelGGL(k_rates, dim3((unsigned)C), dim3(kRatesBlock), bytes, st, T, cells, v_dust,
                        v_frag, Kc, Kf);
@@ -562,17 +570,24 @@ static hipError_t launch_rates_blk(const Tables &T, long C, const CellArrays &ce
     // few blocks (small grids of cells): share each block's pairs among
     // several workgroups, so that at least ~512 run
     const unsigned slices = blocks >= 512 ? 1u : min(8u, (512u + blocks - 1) / blocks);
-    const int tab = rates_blk_tab(T.N, 160 * 1024);
-#define RATES_BLK(TAB)                                                                            \
+    const bool vi = T.vertical != 0;
+    const int tab = rates_blk_tab(T.N, 160 * 1024, vi);
+#define RATES_BLK(TAB, VI)                                                                        \
     {                                                                                             \
-        const size_t bytes = rates_blk_lds_bytes<TAB>(T.N);                                       \
-        if (hipError_t e = allow_lds(k_rates_blk<TAB, OT>, bytes)) return e;                      \
-        hipLaunchKernelGGL((k_rates_blk<TAB, OT>), dim3(blocks, slices), dim3(1024), bytes, st, T,  \
-                           cells, v_dust, v_frag, Kc, Kf, C);                                     \
+        const size_t bytes = rates_blk_lds_bytes<TAB, VI>(T.N);                                   \
+        if (hipError_t e = allow_lds(k_rates_blk<TAB, VI, OT>, bytes)) return e;                  \
+        hipLaunchKernelGGL((k_rates_blk<TAB, VI, OT>), dim3(blocks, slices), dim3(1024), bytes,   \
+                           st, T, cells, v_dust, v_frag, Kc, Kf, C);                              \
     }
-    if (tab == 7) RATES_BLK(7)
-    else if (tab == 6) RATES_BLK(6)
-    else RATES_BLK(1)               // fits LDS for every N <= kMaxBins
+    if (!vi) {
+        if (tab == 7) RATES_BLK(7, false)
+        else if (tab == 6) RATES_BLK(6, false)
+        else RATES_BLK(1, false)    // fits LDS for every N <= kMaxBins
+    } else {
+        if (tab == 7) RATES_BLK(7, true)
+        else if (tab == 6) RATES_BLK(6, true)
+        else RATES_BLK(1, true)
+    }
 #undef RATES_BLK
     return hipGetLastError();
 }

@@ -24,15 +24,18 @@ namespace coag {
 //   dV_I^2  = (St_i - St_j)/(St_i + St_j) (C_i - A_i - q + A_j)
 //   dV_II^2 = 2 (S_i - delta) + C_i - B_i + q - B_j,   q = St_j^2 / (S_i + St_j)
 // ---------------------------------------------------------------------------
-// Constants of one cell.
+// Constants of one cell (H2 = H^2 and alpha for the vertically integrated
+// kernel's scale heights).
 struct CellRate {
-    double delta, vt_scale, kbt, vf, rg_vth, Om;
+    double delta, vt_scale, kbt, vf, rg_vth, Om, H2, alpha;
     bool turb;
 };
 
 __device__ inline CellRate cell_rate(const CellArrays &cells, const double *v_frag, long c) {
     CellRate r;
     const double c_s = cells.c_s[c], alpha = cells.alpha[c];
+    r.H2 = cells.H[c] * cells.H[c];
+    r.alpha = alpha;
     r.turb = alpha > 0.0;
     r.delta = r.turb ? 1.0 / sqrt(alpha * c_s * cells.H[c] / cells.nu_mol[c]) : 0.0;
     r.vt_scale = alpha * c_s * c_s;
@@ -43,12 +46,26 @@ __device__ inline CellRate cell_rate(const CellArrays &cells, const double *v_fr
     return r;
 }
 
-// One grain of one cell: St, A, B, C above, velocity, 1/m, radius; and, for
-// the heavier grain of a pair, S, u = C - A and w = 2 (S - delta) + C - B.
+// One grain of one cell: St, A, B, C above, velocity, 1/m, radius, the
+// squared scale height h^2 (vertically integrated kernel); and, for the
+// heavier grain of a pair, S, u = C - A and w = 2 (S - delta) + C - B.
 struct Grain {
-    double st, a, bt, ct, vx, vy, vz, im, s;
+    double st, a, bt, ct, vx, vy, vz, im, s, h2;
     double S, u, w;
 };
+
+// Vertically integrated kernel (Sec. 5.1): a grain's column has a Gaussian
+// vertical profile of scale height h = H sqrt(alpha / (alpha + St)) (mixing
+// against settling), and its vertical velocity is the terminal settling
+// speed St Omega Z at Z = h.  The pair rate is the volume rate integrated
+// over height: K / sqrt(2 pi (h_i^2 + h_j^2)).  Needs alpha > 0 (h = 0
+// otherwise, and the rates are not finite).
+__device__ inline double grain_h2(const CellRate &r, double st) {
+    return r.H2 * (r.alpha / (r.alpha + st));
+}
+__device__ inline double settle_speed(const CellRate &r, double st, double h2) {
+    return st * r.Om * sqrt(h2);
+}
 
 __device__ inline double stir_s(const CellRate &r, double st) {
     return fmin(fmax(kYStar * st, r.delta), 1.0);
@@ -102,9 +119,10 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 }
 
 // Kc, Kf of the pair (i, j), i >= j (i the grain with the larger St; its
-// heavier_terms set)
+// heavier_terms set); vertical: the vertically integrated kernel (the
+// grains' vz are then their settling speeds, h2 their squared scale heights)
 __device__ inline void pair_rates(const CellRate &r, const Grain &gi, const Grain &gj, bool diag,
-                                  double &kc, double &kf) {
+                                  bool vertical, double &kc, double &kf) {
     double vturb2 = 0.0;
     if (r.turb) {
         const double si = gi.st, sj = gj.st;
@@ -121,7 +139,8 @@ __device__ inline void pair_rates(const CellRate &r, const Grain &gi, const Grai
     const double rs = dv2 > 0.0 ? rsqrt_nr(dv2) : 0.0;
     const double dv = dv2 * rs;
     const double ss = gi.s + gj.s;
-    const double K = M_PI * ss * ss * dv * (diag ? 0.5 : 1.0);
+    double K = M_PI * ss * ss * dv * (diag ? 0.5 : 1.0);
+    if (vertical) K *= rsqrt_nr(2.0 * M_PI * (gi.h2 + gj.h2));
     // past y = kExpZeroY, exp(-y) is zero in FP64 (denormals included), so
     // pf = 0 and pc = 1 exactly; pairs of slowly colliding grains, the most
     // common, then skip the exponential (a branch whole waves take together)
@@ -153,13 +172,28 @@ __device__ inline void pair_rates(const CellRate &r, const Grain &gi, const Grai
 //   dKf/dv_frag = -X Kf / v_frag = -dKc/dv_frag.
 // With alpha = 0 the turbulent term is off and Z = 0; with dv = 0, or where
 // e^-y is zero in FP64 (Kf = 0 there), X = 0.
+//
+// Vertically integrated kernel: alpha also moves the scale heights, with
+// d ln h_k / d alpha = St_k / (2 alpha (alpha + St_k)) = e_k, hence the
+// settling speeds (d vlam^2 / d alpha, passed in as dvlam2_da, joins
+// d v_turb^2 / d alpha in Z) and the overlap factor G = (2 pi (h_i^2 +
+// h_j^2))^(-1/2), whose W = d ln G / d alpha = -(h_i^2 e_i + h_j^2 e_j) /
+// (h_i^2 + h_j^2) adds W Kc, W Kf to the two alpha derivatives (vertical_w).
 struct RateDerivs {
     double Z, X;
 };
 
+__device__ inline double vertical_e(const CellRate &r, double st) {
+    return st / (2.0 * r.alpha * (r.alpha + st));
+}
+
+__device__ inline double vertical_w(double h2_i, double e_i, double h2_j, double e_j) {
+    return -(h2_i * e_i + h2_j * e_j) / (h2_i + h2_j);
+}
+
 __device__ inline RateDerivs pair_rate_derivs(const CellRate &r, double alpha, double cs2,
                                               double st_i, double st_j, double im_i,
-                                              double im_j, double vlam2) {
+                                              double im_j, double vlam2, double dvlam2_da) {
     double vturb2 = 0.0, dvt2_da = 0.0;
     if (r.turb) {
         const double d = r.delta;
@@ -180,7 +214,7 @@ __device__ inline RateDerivs pair_rate_derivs(const CellRate &r, double alpha, d
     RateDerivs o{0.0, 0.0};
     const double dv2 = r.kbt * (im_i + im_j) + vturb2 + vlam2;
     if (!(dv2 > 0.0)) return o;
-    o.Z = dvt2_da / (2.0 * dv2);
+    o.Z = (dvt2_da + dvlam2_da) / (2.0 * dv2);
     const double y = 1.5 * r.vf * r.vf / dv2;
     o.X = y < kExpZeroY ? 2.0 * y * y / (1.0 + y) : 0.0;
     return o;
@@ -198,10 +232,14 @@ __device__ inline RateDerivs pair_rate_derivs(const CellRate &r, double alpha, d
 // read from v_dust); what is left out follows from St where it is used, by
 // the same arithmetic.  Only pairs in [p0, p1) are written (a block's pairs
 // may be shared among several workgroups).
-template <int TAB>
-inline size_t rates_blk_lds_bytes(int N) { return (size_t)(16 * TAB + 2) * N * sizeof(double); }
+// VI (the vertically integrated kernel) adds one value per grain, h^2, and
+// puts the settling speed in the place of the vertical velocity.
+template <int TAB, bool VI>
+inline size_t rates_blk_lds_bytes(int N) {
+    return (size_t)(16 * (TAB + (VI ? 1 : 0)) + 2) * N * sizeof(double);
+}
 
-template <int TAB, int NT, typename OT>
+template <int TAB, bool VI, int NT, typename OT>
 __device__ void rates_block(const Tables &T, const CellArrays &cells,
                             const double *__restrict__ v_dust, const double *__restrict__ v_frag,
                             OT *__restrict__ Kc, OT *__restrict__ Kf, long C, long cell0,
@@ -209,23 +247,26 @@ __device__ void rates_block(const Tables &T, const CellArrays &cells,
     static_assert(TAB == 7 || TAB == 6 || TAB == 1, "tabulated values per grain");
     static_assert(NT % 64 == 0, "whole waves");
     constexpr int VX = TAB - 3;                       // first velocity row (TAB >= 6)
+    constexpr int TW = TAB + (VI ? 1 : 0);            // values per grain; h^2 last
     constexpr int SLOTS = NT / 16;
     const int N = T.N, P = T.P;
-    double *tb = lds, *sv = lds + 16 * TAB * N, *imv = sv + N;
+    double *tb = lds, *sv = lds + 16 * TW * N, *imv = sv + N;
     // [bin][value][cell]: the values of one grain 128 bytes apart, so that
     // a lane reads them all from one address with immediate offsets
-    auto tab = [&](int v, int k, int cl) -> double & { return tb[(k * TAB + v) * 16 + cl]; };
+    auto tab = [&](int v, int k, int cl) -> double & { return tb[(k * TW + v) * 16 + cl]; };
     for (int t = threadIdx.x; t < 16 * N; t += NT) {
         const int cl = t & 15, k = t >> 4;
         const long c = cell0 + cl;
         Grain g{};
         if (c < C) {
-            grain_terms(cell_rate(cells, v_frag, c), T.rho_m, T.s[k], g);
+            const CellRate r = cell_rate(cells, v_frag, c);
+            grain_terms(r, T.rho_m, T.s[k], g);
+            if (VI) g.h2 = grain_h2(r, g.st);
             if (TAB >= 6) {
                 const double *v = v_dust + (c * N + k) * 3;
                 g.vx = v[0];
                 g.vy = v[1];
-                g.vz = v[2];
+                g.vz = VI ? settle_speed(r, g.st, g.h2) : v[2];
             }
         }
         tab(0, k, cl) = g.st;
@@ -237,6 +278,7 @@ __device__ void rates_block(const Tables &T, const CellArrays &cells,
             tab(VX + 1, k, cl) = g.vy;
             tab(VX + 2, k, cl) = g.vz;
         }
+        if (VI) tab(TAB, k, cl) = g.h2;
     }
     for (int k = threadIdx.x; k < N; k += NT) {
         sv[k] = T.s[k];
@@ -262,8 +304,9 @@ __device__ void rates_block(const Tables &T, const CellArrays &cells,
             grain_abc(r, tab(0, k, cl), g);
             g.vx = vc[3 * k];
             g.vy = vc[3 * k + 1];
-            g.vz = vc[3 * k + 2];
+            g.vz = VI ? settle_speed(r, g.st, tab(TAB, k, cl)) : vc[3 * k + 2];
         }
+        g.h2 = VI ? tab(TAB, k, cl) : 0.0;
         g.im = imv[k];
         g.s = sv[k];
         return g;
@@ -281,7 +324,7 @@ __device__ void rates_block(const Tables &T, const CellArrays &cells,
             if (TAB == 6) gi.ct = gi.st * gi.st / (S + gi.st);
             heavier_terms(r, gi, S);
             double c64, f64;
-            pair_rates(r, gi, grain(j), i == j, c64, f64);
+            pair_rates(r, gi, grain(j), i == j, VI, c64, f64);
             oc = (OT)c64;
             of = (OT)f64;
         }
@@ -290,10 +333,13 @@ __device__ void rates_block(const Tables &T, const CellArrays &cells,
     }
 }
 
-// the table size rates_block takes at N bins (7, 6, or 1 values per grain)
-inline int rates_blk_tab(int N, size_t lds_cap) {
-    if (rates_blk_lds_bytes<7>(N) <= lds_cap) return 7;
-    if (rates_blk_lds_bytes<6>(N) <= lds_cap) return 6;
+// the table size rates_block takes at N bins (7, 6, or 1 values per grain,
+// one more for the vertically integrated kernel)
+inline int rates_blk_tab(int N, size_t lds_cap, bool vi) {
+    if ((vi ? rates_blk_lds_bytes<7, true>(N) : rates_blk_lds_bytes<7, false>(N)) <= lds_cap)
+        return 7;
+    if ((vi ? rates_blk_lds_bytes<6, true>(N) : rates_blk_lds_bytes<6, false>(N)) <= lds_cap)
+        return 6;
     return 1;
 }
 

@@ -194,7 +194,7 @@ class ColumnConfig:
     v_frag: float = 100.0        # cm/s
     drift: bool = False          # radial drift and azimuthal lag in v_dust (else zero)
     steps: int = 200
-    dt: float = 100.0 * YEAR     # s per coagulation call
+    dt: float = 1000.0 * YEAR    # s per coagulation call
     rho_m: float = 1.67
     mu: float = 2.4
     sigma0: float = 250.0

@@ -145,7 +145,7 @@ def test_vertical_rate_derivatives_against_complex_step_chain(O):
     rng = np.random.default_rng(11)
     rho = 0.01 * d["cells"]["Sigma_g"][:, None] * rng.uniform(0.2, 1.0, d["rho"].shape) / gv.N
     Kc, Kf = O.rates(gv, d["cells"], d["v_dust"], d["v_frag"])
-    a = O.step(gv, rho, Kc, Kf, d["dt"] * 300, max_sub=64)
+    a = O.step(gv, rho, Kc, Kf, d["dt"] * 30, max_sub=64)
     assert np.all(a["status"] == 0) and np.all(a["nsub"] >= 2)
     g_out = rng.normal(size=rho.shape) / rho.sum(1, keepdims=True)
     g_in, ga, gvf = O.step_backward(gv, d["cells"], d["v_dust"], d["v_frag"], rho, 1.0,
