@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-vertical", action="store_true")
     ap.add_argument("--cpu-sample-cells", type=int, default=512)
     ap.add_argument("--kernel", choices=("batch", "cell"), default="batch",
                     help="FP64 step kernel (cell: one workgroup per cell)")
@@ -402,15 +403,17 @@ class Disc:
         if kernel == "cell":
             os.environ["COAG_STEP_KERNEL"] = "cell"
         self.torch, self.L = torch, L
-        self.cfg = cfg = disc.CONFIGS[cfg_name]
+        # a disc of (R, Z) cells, or columns of the vertically integrated kernel
+        self.vertical = cfg_name in disc.COLUMNS
+        self.cfg = cfg = disc.COLUMNS[cfg_name] if self.vertical else disc.CONFIGS[cfg_name]
         dev = self.dev = "cuda:0"
         m, me, s = coag_mass_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
-        self.d = d = disc.make_disc(cfg, s)
+        self.d = d = disc.make_columns(cfg, s) if self.vertical else disc.make_disc(cfg, s)
         self.C, self.N = cfg.n_cells, cfg.n_bins
         self.kernel = kernel
         self.t = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt,
                                                               device=dev)
-        self.ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
+        self.ctx = coag_create(m, me, s, rho_m=cfg.rho_m, vertical=self.vertical)
         os.environ.pop("COAG_STEP_KERNEL", None)
         self.P = self.ctx.P
         self.cells = {k: self.t(v) for k, v in d["cells"].items()}
@@ -503,7 +506,8 @@ def split_error(D, sample, calls=20):
     b = D.ctx.coag_step(D.t(rho0), *K32, dt, prec=L.PREC_SPLIT_BF16, max_sub=1024)
     torch.cuda.synchronize()
     x, ns, hl = b["rho"].cpu().numpy(), b["nsub"].cpu().numpy(), b["h_log"].cpu().numpy()
-    g = O.make_grid(D.cfg.n_bins, D.cfg.s_min, D.cfg.s_max, rho_m=D.cfg.rho_m)
+    g = O.make_grid(D.cfg.n_bins, D.cfg.s_min, D.cfg.s_max, rho_m=D.cfg.rho_m,
+                    vertical=int(D.vertical))
     oKc, oKf = O.rates(g, sub["cells"], sub["v_dust"], sub["v_frag"])
     ref = O.step(g, rho0, oKc, oKf, dt, mode=O.REPLAY, nsub=ns, h_log=hl)["rho"]
     M = ref.sum(1, keepdims=True)
@@ -519,7 +523,7 @@ def split_error(D, sample, calls=20):
             "status_ok": bool(np.all(b["status"].cpu().numpy() == 0))}
 
 
-def adjoint_ratio(torch, workload, reps=3):
+def adjoint_ratio(torch, workload, reps=3, dt_scale=1.0):
     """Backward / forward time of the same coagulation call on `workload`, in
     FP64 and in split BF16: the first call from the initial state (rates +
     ADAPTIVE step, steps recorded; the split form with FP32 blocked rates),
@@ -534,10 +538,10 @@ def adjoint_ratio(torch, workload, reps=3):
     from paper_2402_18471_amd import _lib as L
     D = Disc(workload, torch)
     rho_in = D.t(D.d["rho"])
-    dt = float(D.d["dt"])
+    dt = float(D.d["dt"]) * dt_scale
     P, N = D.P, D.N
     g_out = torch.ones((D.C, D.N), dtype=torch.float64, device=D.dev) / rho_in.sum(1, keepdim=True)
-    out = {"workload": D.cfg.name, "cells": D.C}
+    out = {"workload": D.cfg.name, "cells": D.C, "dt_yr": dt / 3.15576e7}
     for name, prec in (("fp64", L.PREC_FP64), ("split_bf16", L.PREC_SPLIT_BF16)):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         fwd, bwd = [], []
@@ -574,6 +578,31 @@ def adjoint_ratio(torch, workload, reps=3):
                    "+ ADAPTIVE step; backward recomputes the rates, their derivative factors and "
                    "the stage states, then runs the reverse sweep; backward_roofline: the "
                    "backward's algorithmic bytes (see bench.py adjoint_ratio) over its time")
+    return out
+
+
+def vertical_columns(torch, workload, steps=10, warmup=2):
+    """The vertically integrated kernel on `workload` (columns, surface
+    densities): FP64 and split-BF16 calls with the state carried, the split
+    form's error against the FP64 oracle on a sample of columns, and the
+    adjoint's backward / forward time in both precisions."""
+    D = Disc(workload, torch)
+    out = {"workload": D.cfg.name, "columns": D.C, "bins": D.N,
+           "dt_yr": D.cfg.dt / 3.15576e7}
+    for name, split in (("fp64", False), ("split_bf16", True)):
+        r = D.forward(steps, warmup, split)
+        out[name] = {"value": r["acc"] / r["wall"], "unit": "cell-steps/s",
+                     "ms_per_step": r["wall"] / steps * 1e3,
+                     "rates_ms": float(r["rates_ms"].mean()),
+                     "step_ms": float(r["step_ms"].mean()), "cells_failed": r["failed"],
+                     "accepted_substeps_per_call": r["acc"] / (steps * D.C)}
+    out["split_bf16"]["speedup_vs_fp64"] = out["split_bf16"]["value"] / out["fp64"]["value"]
+    out["split_bf16"]["error_vs_oracle"] = split_error(D, np.arange(0, D.C, max(1, D.C // 64)),
+                                                       calls=1)
+    a = adjoint_ratio(torch, workload, reps=1, dt_scale=0.3)
+    out["adjoint"] = {"dt_yr": a["dt_yr"], **{k: {"adjoint_over_forward": a[k]["adjoint_over_forward"],
+                                                  "backward_ms": a[k]["backward_ms"]}
+                                              for k in ("fp64", "split_bf16")}}
     return out
 
 
@@ -662,6 +691,9 @@ def main():
         progress("adjoint timed on the 64x32 x 100 disc")
         out["adjoint_on_bench_disc"] = adjoint_ratio(torch, args.config, reps=2)
         progress(f"adjoint timed on {args.config}")
+    if not args.no_vertical:
+        out["vertical"] = vertical_columns(torch, "col4096_n200")
+        progress("vertically integrated kernel timed on 4096 columns")
     if not args.no_cpu_baseline:
         progress("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(D.cfg, disc, args.cpu_sample_cells)
