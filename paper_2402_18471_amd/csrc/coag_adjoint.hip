@@ -404,9 +404,13 @@ __global__ __launch_bounds__(kBBlock) void k_adj_batch(Tables T, BatchTables B, 
         uint4 A16[2][6];
         auto load_a = [&](int ch, int set) {
             if (PREC == 0) {
-                const double *at = B.a64 + (long)ch * 8 * 64 + lane;
+                const double2 *at = (const double2 *)B.a64 + (long)ch * 4 * 64 + lane;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) A64[set][e] = at[e * 64];
+                for (int u = 0; u < 4; ++u) {
+                    const double2 v = at[u * 64];
+                    A64[set][2 * u] = v.x;
+                    A64[set][2 * u + 1] = v.y;
+                }
             } else {
                 const uint4 *at = B.a16 + (long)ch * 2 * 3 * 32 + (lane & 31);
                 const int l0 = hk ? 1 : 2, l1 = hk ? 1 : 0;

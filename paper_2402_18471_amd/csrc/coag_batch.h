@@ -16,13 +16,15 @@ namespace coag {
 //   column block (crow_c, split form).  Every product of row i (coagulation
 //   and remnant targets, and bin i itself, which loses m_i per collision) lies
 //   in the 16-bin window [wb[i], wb[i] + 16).
-//   b64: FP64 B operands of v_mfma_f64_16x16x4f64 in crow order, [NC][8][64]
+//   b64: FP64 B operands of v_mfma_f64_16x16x4f64 in crow order, [NC][4][64][2]
+//        (operand s of lane l at [s / 2][l][s % 2]: a lane's pairs of operands
+//        are 16-byte loads, contiguous over the wave)
 //   b16: three BF16 limbs of the same entries for v_mfma_f32_16x16x32_bf16, in
 //        crow_c order, [NC][3][64] x 16 bytes
 //   a64: the same entries as A operands of the adjoint's v_mfma_f64_16x16x4f64
-//        (pairs as rows, bins as the K dimension), crow_c order,
-//        [NC][2 kinds][4 bin quads][64]: lane l holds pair 16q + l % 16, bin
-//        wb[i] + 4 t + l / 16
+//        (pairs as rows, bins as the K dimension), crow_c order, operand
+//        e = 4 kind + t of lane l at [NC][e / 2][64][e % 2] (16-byte loads):
+//        lane l holds pair 16q + l % 16, bin wb[i] + 4 t + l / 16
 //   a16: three BF16 limbs of the adjoint's A operands of
 //        v_mfma_f32_16x16x32_bf16, crow_c order, [NC][2 kinds][3 limbs][32] x
 //        16 bytes: entry l holds pair 16q + l % 16, bins wb[i] + 8 (l / 16) + e,

@@ -40,7 +40,7 @@ using namespace bc;
 
 // chunks of rates in flight per wave: the FP64 form has the registers for a
 // deeper ring (one 8-wave workgroup per CU either way)
-constexpr int kRing64 = 4, kRing16 = 2;
+constexpr int kRing64 = 2, kRing16 = 2;
 static_assert(kRing64 % 2 == 0 && kRing16 % 2 == 0,
               "the D operands alternate between two register sets by chunk parity");
 
@@ -109,7 +109,8 @@ __global__ void k_batch_b(Tables T, int NC, const int *crow, const int *crow_c, 
     int bin = wb[i] + (lane & 15);
     // FP64 operand of MFMA s: K row g <-> pair 16q + 4g + s % 4, kind s / 4
     for (int s = 0; s < 8; ++s)
-        b64[((long)ch * 8 + s) * 64 + lane] = d_entry(T, i, 16 * q + 4 * g + (s & 3), s >> 2, bin);
+        b64[(((long)ch * 4 + (s >> 1)) * 64 + lane) * 2 + (s & 1)] =
+            d_entry(T, i, 16 * q + 4 * g + (s & 3), s >> 2, bin);
     // BF16 operand (chunks in the split form's order): K rows 8g + e <-> pair
     // 16q + 4g + e % 4, kind e / 4 (both kinds of four pairs in one lane)
     i = crow_c[ch] & 0xffff;
@@ -141,9 +142,11 @@ __global__ void k_adj_a(Tables T, int NC, const int *crow_c, const int *wb, doub
     const int i = crow_c[ch] & 0xffff, q = crow_c[ch] >> 16;
     const int j = 16 * q + (lane & 15);
     for (int kind = 0; kind < 2; ++kind)
-        for (int tq = 0; tq < 4; ++tq)
-            a64[(((long)ch * 2 + kind) * 4 + tq) * 64 + lane] =
+        for (int tq = 0; tq < 4; ++tq) {
+            const int e = kind * 4 + tq;            // operand e of the lane
+            a64[(((long)ch * 4 + (e >> 1)) * 64 + lane) * 2 + (e & 1)] =
                 d_entry(T, i, j, kind, wb[i] + 4 * tq + (lane >> 4));
+        }
     if (lane >= 32) return;
     for (int kind = 0; kind < 2; ++kind) {
         union {
@@ -347,38 +350,52 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         int ci = cr0 & 0xffff, cq = cr0 >> 16;     // chunk being processed
         int ri = ci, rq = cq;                       // next chunk to load rates for
         int cur = ci;
-        f64x4 acc64 = {0.0, 0.0, 0.0, 0.0};
+        // two accumulators, coagulating and fragmenting products, so that the
+        // chunk's matrix products form two dependent chains of four, not one
+        // of eight
+        f64x4 acc64 = {0.0, 0.0, 0.0, 0.0}, acf64 = {0.0, 0.0, 0.0, 0.0};
         // accumulator layout of v_mfma_f64_16x16x4f64: lane l, register r ->
         // row (cell) l / 16 + 4 r, column (bin) l % 16
         auto flush = [&](int i) {
             const int bin = wbl[i] + cl;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) atomicAdd(&net[(g + 4 * r) * NS + bin], acc64[r]);
+            for (int r = 0; r < 4; ++r)
+                atomicAdd(&net[(g + 4 * r) * NS + bin], acc64[r] + acf64[r]);
         };
         // the batch's rates: reordered in the workspace ([P][kind][16]), or the
-        // caller's 16-cell-blocked arrays ([P][16] per kind)
+        // caller's 16-cell-blocked arrays ([P][16] per kind), read through
+        // raw buffers over the batch (byte offsets below 2^32 for N <= 1023)
         const RT *kcb = BLK ? (const RT *)a.Kc + cell0 * P : kb;
         const RT *kfb = BLK ? (const RT *)a.Kf + cell0 * P : kb + kBC;
-        constexpr long kps = BLK ? kBC : 2 * kBC;
+        constexpr unsigned kps = BLK ? kBC : 2 * kBC;
+        const unsigned span = (unsigned)((P * kps + kBC) * sizeof(RT));
+        const __amdgpu_buffer_rsrc_t kcr = raw_buffer(kcb, span), kfr = raw_buffer(kfb, span);
         // lane (cell, g): pairs 16q + 4g + s, s = 0..3, both kinds
         double rkc[kRing64][4], rkf[kRing64][4], bb[2][8];
         auto load_k = [&](int i, int q, double (&kc)[4], double (&kf)[4]) {
-            const long prow = (long)i * (i + 1) / 2;
+            const unsigned prow = (unsigned)(i * (i + 1) / 2);
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int j = 16 * q + 4 * g + s;
-                const long o = (prow + (j <= i ? j : i)) * kps + cl;
+                const unsigned o =
+                    ((prow + (unsigned)(j <= i ? j : i)) * kps + (unsigned)cl) * sizeof(RT);
                 // streaming loads: the rates are read once per right-hand
                 // side, and keeping them out of L2 leaves it to the D
                 // operands every batch shares (9 % less traffic, 2 % faster)
-                kc[s] = (double)__builtin_nontemporal_load(&kcb[o]);
-                kf[s] = (double)__builtin_nontemporal_load(&kfb[o]);
+                kc[s] = buf_f64<true>(kcr, o);
+                kf[s] = buf_f64<true>(kfr, o);
             }
         };
+        // the chunk's eight operands of this lane as four 16-byte loads, each
+        // contiguous over the wave
         auto load_b = [&](int ch, double (&b)[8]) {
-            const double *bt = B.b64 + (long)ch * 8 * 64 + lane;
+            const double2 *bt = (const double2 *)B.b64 + (long)ch * 4 * 64 + lane;
 #pragma unroll
-            for (int s = 0; s < 8; ++s) b[s] = bt[s * 64];
+            for (int u = 0; u < 4; ++u) {
+                const double2 v = bt[u * 64];
+                b[2 * u] = v.x;
+                b[2 * u + 1] = v.y;
+            }
         };
         int rleft = c1 - c0;                        // chunks whose rates are still to load
         auto next_k = [&](double (&kc)[4], double (&kf)[4]) {
@@ -399,6 +416,7 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
                 flush(cur);
                 cur = i;
                 acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
+                acf64 = f64x4{0.0, 0.0, 0.0, 0.0};
                 ni = nrow[i];
                 mi = mk[i];
                 fri = frow[i];
@@ -429,11 +447,10 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             }
             const double(&b)[8] = bb[u & 1];
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int s = 0; s < 4; ++s) {
                 acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rc[s], b[s], acc64, 0, 0, 0);
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-                acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rf[s], b[4 + s], acc64, 0, 0, 0);
+                acf64 = __builtin_amdgcn_mfma_f64_16x16x4f64(rf[s], b[4 + s], acf64, 0, 0, 0);
+            }
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 atomicAdd(&netc[jc[s]], loss[s]);
@@ -488,12 +505,15 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         f32x4 acc32[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
         // accumulator layout of v_mfma_f32_16x16x32_bf16: lane l, register r ->
         // row (cell) 4 (l / 16) + r, column (bin) l % 16
+        double tmax[4];                             // max n of the tile's cells 4g + r
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tmax[r] = ctl[4 * g + r].nmax;
         auto flush_tile = [&](int i, int t) {
             const int bin = wbl[i] + cl;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int c = 4 * g + r;
-                const double f = nv[c * NS + i] * ctl[c].nmax;
+                const double f = nv[c * NS + i] * tmax[r];
                 atomicAdd(&net[c * NS + bin], f * (double)acc32[t][r]);
             }
             acc32[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -542,20 +562,34 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         // FP32 rates: pair p of the batch's cell cl at p * 16 + cl (padding
         // cells hold zeros); FP64 rates: [C][P], cells past C read cell C - 1
         constexpr bool blk = BLK;
-        constexpr long ks = blk ? 16 : 1;
+        constexpr unsigned ks = blk ? 16 : 1;
         const long cb = cell0 + cl < C ? cell0 + cl : C - 1;
-        const long kbase = blk ? cell0 * P + cl : cb * P;
+        // blocked rates: the batch's uniform base and 32-bit lane offsets
+        // (pair p of cell cl at p * 16 + cl); [C][P] rates: the lane's cell
+        // both from the batch's first cell: blocked, pair p of cell cl at
+        // p * 16 + cl; [C][P], at (cb - cell0) * P + p (cells past C read
+        // cell C - 1); byte offsets below 2^32 for N <= 1023
+        const long kbase = cell0 * P;
+        const unsigned kl = blk ? (unsigned)cl : (unsigned)((cb - cell0) * P);
         const RT *Kc = (const RT *)a.Kc + kbase, *Kf = (const RT *)a.Kf + kbase;
+        const long ncb = C - cell0 < kBC ? C - cell0 : kBC;
+        const unsigned span = (unsigned)((blk ? P * ks + kBC : ncb * P) * sizeof(RT));
+        const __amdgpu_buffer_rsrc_t kcr = raw_buffer(Kc, span), kfr = raw_buffer(Kf, span);
         RT rk[kRing16][8];
         uint4 bb[2][3];
         auto load_k = [&](int i, int q, RT (&k)[8]) {
-            const long prow = (long)i * (i + 1) / 2;
+            const unsigned prow = (unsigned)(i * (i + 1) / 2);
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int j = 16 * q + 4 * g + s;
-                const long o = (prow + (j <= i ? j : i)) * ks;
-                k[s] = Kc[o];
-                k[4 + s] = Kf[o];
+                const unsigned o = ((prow + (unsigned)(j <= i ? j : i)) * ks + kl) * sizeof(RT);
+                if constexpr (sizeof(RT) == 4) {
+                    k[s] = buf_f32<false>(kcr, o);
+                    k[4 + s] = buf_f32<false>(kfr, o);
+                } else {
+                    k[s] = buf_f64<false>(kcr, o);
+                    k[4 + s] = buf_f64<false>(kfr, o);
+                }
             }
         };
         auto load_b = [&](int ch, uint4 (&b)[3]) {

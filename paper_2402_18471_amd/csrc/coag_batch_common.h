@@ -87,6 +87,24 @@ __device__ __forceinline__ double wave_min_d(double v) {
 // folds them onto 32 / 2^(k-1) banks: 8-way conflicts at N = 80, 4-way at 200)
 __host__ __device__ constexpr int batch_row_stride(int N) { return N | 1; }
 
+// A raw buffer over `bytes` bytes from base (a wave-uniform pointer): loads
+// through it take a 32-bit byte offset per lane, with no 64-bit address
+// arithmetic in the vector unit, and read zero past the end.  The fourth
+// descriptor word is the gfx9 raw-buffer format (32-bit data).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void *base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+// a double / a float at byte offset off; nt: non-temporal (streamed once)
+template <bool NT>
+__device__ __forceinline__ double buf_f64(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, NT ? 2 : 0));
+}
+template <bool NT>
+__device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, NT ? 2 : 0));
+}
+
 // The batch a workgroup takes.  Workgroups are dealt to the eight XCDs in
 // turn (workgroup w to XCD w mod 8), and each XCD runs its share from its own
 // queue, so with the plain mapping XCD x would take every batch b = x mod 8:
