@@ -112,15 +112,17 @@ def evolve_memory_plan(C, N, calls, ckpt, width, prec_split):
     compacted step logs (width per call, an upper bound) and step counts,
     one segment's start states, and the state, its gradient and g_out."""
     P = N * (N + 1) // 2
+    m = N >> 1
+    SL = (m + 1) ** 2 if N & 1 else m * (m + 1)          # pair slots per 16-cell block
     Cb = -(-C // 16) * 16
     al = lambda b: -(-b // 256) * 256
-    rates = 2 * Cb * P * 4 if prec_split else 2 * C * P * 8 + Cb * P * 2 * 8
+    rates = Cb // 16 * 64 * SL * 4 if prec_split else 2 * C * P * 8 + Cb // 16 * 64 * SL * 8
     slopes = al(Cb * 5 * N * 8)
 
     def adj(S):
         Sb = -(-S // 16) * 16
         rt, gt = (4, 4) if prec_split else (8, 8)
-        return (2 * al(rt * P * Sb) + 2 * al(gt * P * Sb) + al(8 * N * (width + 1) * S) +
+        return (al(rt * 64 * SL * (Sb // 16)) + 2 * al(gt * P * Sb) + al(8 * N * (width + 1) * S) +
                 al(8 * N * 2 * width * S) + al(8 * N * S) + al(Sb * 5 * N * 8) + al(4 * S) +
                 al(8 * N * S))
     if adj(C) <= ADJ_BUDGET:
@@ -443,9 +445,10 @@ class Disc:
         nrej = torch.zeros((n, C), dtype=torch.int32, device=self.dev)
         status = torch.zeros(C, dtype=torch.int32, device=self.dev)
         max_sub = 4096
+        # blocked: both kinds in Kc, Kf unused
         Kc = torch.empty(self.ctx.blocked_shape(C) if blk else (C, self.P),
                          dtype=torch.float32 if f32 else torch.float64, device=self.dev)
-        Kf = torch.empty_like(Kc)
+        Kf = None if blk else torch.empty_like(Kc)
         tol = L.Tol(1e-2, 1e-10, 1e-12, max_sub, L.ADAPTIVE,
                     L.PREC_SPLIT_BF16 if split else L.PREC_FP64, 0,
                     L.RATES_BLK32 if f32 else (L.RATES_BLK64 if blk else L.RATES_CP64))
@@ -458,8 +461,7 @@ class Disc:
             e[0].record(self.stream)
             if blk:
                 L.check(self.lib.coag_rates_blocked(h_, C, ct.byref(self.cs), p(self.v_dust),
-                                                    p(self.v_frag), 1 if f32 else 0, p(Kc), p(Kf),
-                                                    sp), h_)
+                                                    p(self.v_frag), 1 if f32 else 0, p(Kc), sp), h_)
             else:
                 L.check(self.lib.coag_rates(h_, C, ct.byref(self.cs), p(self.v_dust),
                                             p(self.v_frag), p(Kc), p(Kf), sp), h_)
@@ -503,7 +505,7 @@ def split_error(D, sample, calls=20):
     rho0 = sub["rho"]
     dt = calls * float(D.d["dt"])
     K32 = D.ctx.coag_rates_blocked(cells, vd, vf)
-    b = D.ctx.coag_step(D.t(rho0), *K32, dt, prec=L.PREC_SPLIT_BF16, max_sub=1024)
+    b = D.ctx.coag_step(D.t(rho0), K32, None, dt, prec=L.PREC_SPLIT_BF16, max_sub=1024)
     torch.cuda.synchronize()
     x, ns, hl = b["rho"].cpu().numpy(), b["nsub"].cpu().numpy(), b["h_log"].cpu().numpy()
     g = O.make_grid(D.cfg.n_bins, D.cfg.s_min, D.cfg.s_max, rho_m=D.cfg.rho_m,
@@ -549,7 +551,7 @@ def adjoint_ratio(torch, workload, reps=3, dt_scale=1.0):
             rho = rho_in.clone()
             ev[0].record(D.stream)
             if prec == L.PREC_SPLIT_BF16:
-                Kc, Kf = D.ctx.coag_rates_blocked(D.cells, D.v_dust, D.v_frag)
+                Kc, Kf = D.ctx.coag_rates_blocked(D.cells, D.v_dust, D.v_frag), None
             else:
                 Kc, Kf = D.ctx.coag_rates(D.cells, D.v_dust, D.v_frag)
             a = D.ctx.coag_step(rho, Kc, Kf, dt, max_sub=64, prec=prec, check_status=False)

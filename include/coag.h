@@ -75,12 +75,23 @@ enum { COAG_PREC_FP64 = 0, COAG_PREC_SPLIT_BF16 = 1 };
 enum { COAG_ADAPTIVE = 0, COAG_FIXED = 1, COAG_REPLAY = 2 };
 
 /* layouts of the rates handed to coag_step (coag_tol.rates_layout):
-   CP64  : double [C][P], pair p of cell c at c * P + p (coag_rates);
-   BLK32 : float, 16-cell-blocked: [ceil(C/16)][P][16], pair p of cell c at
-           ((c / 16) * P + p) * 16 + c % 16 (coag_rates_blocked, f32 = 1);
-   BLK64 : double, the same 16-cell-blocked order (coag_rates_blocked, f32 = 0).
-   A blocked array holds ceil(C/16) * 16 * P values; the padding cells of the
-   last block are read and must be finite (coag_rates_blocked writes zeros). */
+   CP64  : double, two arrays Kc, Kf [C][P], pair p of cell c at c * P + p
+           (coag_rates);
+   BLK32 : float, 16-cell-blocked, both kinds in one array (coag_rates_blocked,
+           f32 = 1);
+   BLK64 : double, 16-cell-blocked, both kinds in one array (coag_rates_blocked,
+           f32 = 0).
+   Blocked: per block of 16 cells (cells 16 b .. 16 b + 15) the pairs of each
+   row i are taken two by two: pair (i, j) lies in slot S(i) + j / 2 of the
+   block with parity u = j & 1, S(i) = m (m + 1) for i = 2m and (m + 1)^2 for
+   i = 2m + 1 (a row of odd length ends with the zero entry (i, i + 1)); S(N)
+   slots of 64 values per block, 64 S(N) ceil(C/16) values in all.  Kind k
+   (0: Kc, 1: Kf) of cell c of the block in slot s at, within the block,
+     BLK64 ((s * 2 + u) * 16 + c % 16) * 2 + k
+     BLK32 ((s * 16 + c % 16) * 2 + u) * 2 + k
+   the order in which one 16-byte load per lane of a wave is contiguous.  The
+   padding cells of the last block and the zero entries are read and must be
+   finite (coag_rates_blocked writes zeros). */
 enum { COAG_RATES_CP64 = 0, COAG_RATES_BLK32 = 1, COAG_RATES_BLK64 = 2 };
 
 /* Mass grid and collision-outcome parameters (Sec. 5).  HOST arrays, copied
@@ -173,15 +184,16 @@ int coag_rates(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *
                const double *v_frag, double *Kc, double *Kf, void *stream);
 
 /* The same rates in the 16-cell-blocked layout (COAG_RATES_BLK32 / BLK64
-   above): f32 = 1 rounds them to float, for the split-BF16 step, which then
-   streams half the bytes per right-hand side; f32 = 0 keeps double, for the
-   batched FP64 step.  Either way the 16 cells of a pair are one contiguous run
-   (64 or 128 bytes), so the batched step reads whole cache lines with no
-   reordering of its own.  Kc, Kf DEVICE out, ceil(C/16) * 16 * P elements
-   each, caller-owned; the padding cells of the last block are written as
-   zeros.  Errors as coag_rates, and COAG_EINVAL for f32 not 0 or 1. */
+   above), both kinds in one array: f32 = 1 rounds them to float, for the
+   split-BF16 step, which then streams half the bytes per right-hand side;
+   f32 = 0 keeps double, for the batched FP64 step.  The batched kernels read
+   them in place with one 16-byte load per lane and pair (double) or two pairs
+   (float), whole cache lines over a wave.  K DEVICE out, 64 S(N) ceil(C/16)
+   elements, caller-owned; the padding cells of the last block and the zero
+   entries are written as zeros.  Errors as coag_rates, and COAG_EINVAL for
+   f32 not 0 or 1. */
 int coag_rates_blocked(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
-                       const double *v_frag, int32_t f32, void *Kc, void *Kf, void *stream);
+                       const double *v_frag, int32_t f32, void *K, void *stream);
 
 /* Right-hand side of eq. `smol` for C cells:
      drho_k = sum_{i, j<=i} n_i n_j [Kc (m_i+m_j) C_ijk + Kf (m_rem R_ijk + m_frag F_ijk)]
@@ -206,7 +218,7 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
      rho     [C][N]        DEVICE in/out
      Kc, Kf                DEVICE in, in tol->rates_layout: double [C][P] (from
                            coag_rates, or any kernel), or 16-cell-blocked float or
-                           double (from coag_rates_blocked)
+                           double in Kc alone (from coag_rates_blocked; Kf NULL)
      h       [C]           DEVICE in/out (ADAPTIVE): h <= 0 on entry starts with dt;
                            on exit the controller's next (unclipped) step size
      nsub    [C] int32     DEVICE out (ADAPTIVE: accepted steps) or in (FIXED, REPLAY)
@@ -228,7 +240,7 @@ int coag_rhs(coag_ctx *ctx, int64_t C, const double *rho, const double *Kc, cons
        grid conditions (else COAG_ENOTSUP).
    Errors: COAG_EINVAL (null pointer, C < 0, dt <= 0, rtol <= 0, max_sub < 1,
    unknown mode, precision or rates layout, a layout the precision does not
-   take), COAG_ENOTSUP (split precision or blocked rates on a grid the batched
+   take, a non-NULL Kf with blocked rates), COAG_ENOTSUP (split precision or blocked rates on a grid the batched
    step does not cover; blocked FP64 rates with COAG_STEP_KERNEL=cell),
    COAG_ENOMEM. */
 int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void *Kf,
@@ -240,11 +252,11 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void 
    forbid hipMalloc): the same arguments, checks, kernels and results as
    coag_step, with the batched step's workspace taken from a static 64 MiB
    array that the library holds on each device from its load to the end of
-   the process, instead of the context's workspace.  That is room for 16 P +
-   40 N bytes per cell: e.g. 8388 cells of 200 bins with blocked rates
-   (COAG_RATES_BLK32 / BLK64; 40 N bytes per cell), and about 200 cells of
-   200 bins with [C][P] FP64 rates in the FP64 step (which reorders them
-   there).  Larger calls return COAG_EINVAL and launch nothing; split them
+   the process, instead of the context's workspace.  That is room for
+   40 N bytes per cell with blocked rates (COAG_RATES_BLK32 / BLK64: e.g. 8388
+   cells of 200 bins), and 4 S(N) + 40 N (about 16 P + 48 N) bytes per cell
+   with [C][P] FP64 rates in the FP64 step, which reorders them there (about
+   200 cells of 200 bins).  Larger calls return COAG_EINVAL and launch nothing; split them
    into smaller ones.  Every call on one device shares that device's array:
    calls that may overlap on one device (other streams, other contexts, other
    host threads) race and must be serialised by the caller.  Nothing in the

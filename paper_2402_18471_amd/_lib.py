@@ -68,7 +68,7 @@ def load():
         "coag_destroy": (None, [_vp]),
         "coag_last_error": (ct.c_char_p, [_vp]),
         "coag_rates": (ct.c_int, [_vp, i64, P(Cells), _vp, _vp, _vp, _vp, _vp]),
-        "coag_rates_blocked": (ct.c_int, [_vp, i64, P(Cells), _vp, _vp, i32, _vp, _vp, _vp]),
+        "coag_rates_blocked": (ct.c_int, [_vp, i64, P(Cells), _vp, _vp, i32, _vp, _vp]),
         "coag_rhs": (ct.c_int, [_vp, i64, _vp, _vp, _vp, _vp, _vp]),
         "coag_step": (ct.c_int, [_vp, i64, _vp, _vp, _vp, ct.c_double, _vp, P(Tol), _vp, _vp,
                                  _vp, _vp, _vp]),

@@ -23,12 +23,13 @@ from . import _lib as L
 
 
 def _rates(coag, cells, v_dust, vf, prec, out=None):
-    """The rates one call's step reads: FP32, 16-cell-blocked for the split
-    form; FP64 [C][P] for the FP64 form; into `out` (a pair from an earlier
-    call) when given, so that a run holds one pair of rate arrays."""
+    """The rates one call's step reads, as the (Kc, Kf) coag_step takes: FP32,
+    16-cell-blocked for the split form (both kinds in Kc, Kf None); FP64
+    [C][P] for the FP64 form; into `out` (from an earlier call) when given,
+    so that a run holds one set of rate arrays."""
     Kc, Kf = out if out is not None else (None, None)
     if prec == L.PREC_SPLIT_BF16:
-        return coag.coag_rates_blocked(cells, v_dust, vf, dtype=torch.float32, Kc=Kc, Kf=Kf)
+        return coag.coag_rates_blocked(cells, v_dust, vf, dtype=torch.float32, K=Kc), None
     return coag.coag_rates(cells, v_dust, vf, Kc=Kc, Kf=Kf)
 
 

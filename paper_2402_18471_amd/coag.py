@@ -102,13 +102,15 @@ class CoagContext:
         return Kc, Kf
 
     def blocked_shape(self, C):
-        """Shape of the 16-cell-blocked rates of C cells: the rate of cell c,
-        pair p at [c // 16, p, c % 16]."""
-        return ((C + 15) // 16, self.P, 16)
+        """Shape of the 16-cell-blocked rates of C cells (both kinds in one
+        array; the layout of COAG_RATES_BLK32 / BLK64 in include/coag.h):
+        [ceil(C / 16)][slots][64]."""
+        return ((C + 15) // 16, pair_slots(self.N), 64)
 
-    def coag_rates_blocked(self, cells, v_dust, v_frag, dtype=torch.float32, Kc=None, Kf=None):
-        """The rates in the 16-cell-blocked layout (blocked_shape(C)), float32
-        (for split-precision steps) or float64 (for the batched FP64 step)."""
+    def coag_rates_blocked(self, cells, v_dust, v_frag, dtype=torch.float32, K=None):
+        """The rates in the 16-cell-blocked layout (blocked_shape(C)), both
+        kinds in one tensor, float32 (for split-precision steps) or float64
+        (for the batched FP64 step); coag_step takes it as Kc with Kf None."""
         if dtype not in (torch.float32, torch.float64):
             raise TypeError("dtype must be torch.float32 or torch.float64")
         C = int(v_frag.shape[0])
@@ -116,12 +118,11 @@ class CoagContext:
         _dev(v_dust, shape=(C, self.N, 3), name="v_dust")
         _dev(v_frag, shape=(C,), name="v_frag")
         dev, shp = v_frag.device, self.blocked_shape(C)
-        Kc = torch.empty(shp, dtype=dtype, device=dev) if Kc is None else _dev(Kc, dtype, shp, "Kc")
-        Kf = torch.empty(shp, dtype=dtype, device=dev) if Kf is None else _dev(Kf, dtype, shp, "Kf")
+        K = torch.empty(shp, dtype=dtype, device=dev) if K is None else _dev(K, dtype, shp, "K")
         self._check(self._lib.coag_rates_blocked(self._h, C, ct.byref(cs), _ptr(v_dust), _ptr(v_frag),
-                                                 1 if dtype == torch.float32 else 0,
-                                                 _ptr(Kc), _ptr(Kf), _stream()))
-        return Kc, Kf
+                                                 1 if dtype == torch.float32 else 0, _ptr(K),
+                                                 _stream()))
+        return K
 
     def coag_rhs(self, rho, Kc, Kf, out=None):
         C = int(rho.shape[0])
@@ -137,8 +138,8 @@ class CoagContext:
                   h_log=None, log=True, check_status=True, noalloc=False):
         """Advances rho (in place) by dt; returns dict(rho, h, nsub, nrej, h_log, status).
         Kc, Kf: float64 [C][P] from coag_rates, or the 16-cell-blocked rates
-        of coag_rates_blocked (float32: split precision only; float64: FP64
-        only).  check_status: wait for the call and raise CoagCellError if any
+        of coag_rates_blocked as Kc with Kf None (float32: split precision
+        only; float64: FP64 only).  check_status: wait for the call and raise CoagCellError if any
         cell's status is not COAG_CELL_OK (the failed cells keep the state
         the call left them in); False returns at once, with the per-cell
         status for the caller to inspect.  noalloc: call coag_step_noalloc,
@@ -149,11 +150,13 @@ class CoagContext:
         _dev(rho, shape=(C, self.N), name="rho")
         if Kc.dim() == 3:
             layout = L.RATES_BLK32 if Kc.dtype == torch.float32 else L.RATES_BLK64
-            rdt, shp = Kc.dtype, self.blocked_shape(C)
+            _dev(Kc, dtype=Kc.dtype, shape=self.blocked_shape(C), name="K")
+            if Kf is not None:
+                raise ValueError("blocked rates hold both kinds: pass Kf=None")
         else:
-            layout, rdt, shp = L.RATES_CP64, torch.float64, (C, self.P)
-        _dev(Kc, dtype=rdt, shape=shp, name="Kc")
-        _dev(Kf, dtype=rdt, shape=shp, name="Kf")
+            layout = L.RATES_CP64
+            _dev(Kc, shape=(C, self.P), name="Kc")
+            _dev(Kf, shape=(C, self.P), name="Kf")
         if h is None:
             h = torch.zeros(C, dtype=torch.float64, device=dev)
         _dev(h, shape=(C,), name="h")
@@ -203,3 +206,57 @@ class CoagContext:
 
 def coag_create(m, m_edge, s, **kw) -> CoagContext:
     return CoagContext(m, m_edge, s, **kw)
+
+
+def pair_slots(N):
+    """Slots of two pairs per 16-cell block of the blocked rate layout:
+    rows taken two pairs at a time, S(N) = m (m + 1) for N = 2m, (m + 1)^2
+    for N = 2m + 1."""
+    m = N >> 1
+    return (m + 1) ** 2 if N & 1 else m * (m + 1)
+
+
+def _blocked_index(N, f32):
+    """[P][16]: the position, within a block of the blocked layout, of the
+    coagulating rate (kind 0; kind 1 follows it) of pair p, cell c."""
+    i = np.repeat(np.arange(N), np.arange(1, N + 1))
+    j = np.concatenate([np.arange(k + 1) for k in range(N)])
+    m = i >> 1
+    sl = np.where(i & 1, (m + 1) ** 2, m * (m + 1)) + (j >> 1)
+    u, c = (j & 1)[:, None], np.arange(16)[None, :]
+    if f32:
+        return ((sl[:, None] * 16 + c) * 2 + u) * 2
+    return ((sl[:, None] * 2 + u) * 16 + c) * 2
+
+
+def unblock(K, C):
+    """Host copies of blocked rates as (Kc, Kf) [C][P] numpy arrays, and the
+    values the layout holds besides them (padding cells, zero entries)."""
+    x = K.detach().cpu().numpy() if isinstance(K, torch.Tensor) else np.asarray(K)
+    nb, S = x.shape[0], x.shape[1]
+    N = next(n for n in range(1, 1024) if pair_slots(n) == S)
+    idx = _blocked_index(N, x.dtype == np.float32)
+    flat = x.reshape(nb, -1)
+    kc = flat[:, idx].transpose(0, 2, 1).reshape(nb * 16, -1)
+    kf = flat[:, idx + 1].transpose(0, 2, 1).reshape(nb * 16, -1)
+    used = np.zeros(flat.shape[1], bool)
+    used[idx.ravel()] = True
+    used[idx.ravel() + 1] = True
+    rest = np.concatenate([kc[C:].ravel(), kf[C:].ravel(), flat[:, ~used].ravel()])
+    return kc[:C], kf[:C], rest
+
+
+def block(Kc, Kf, dtype=torch.float64, device="cuda:0"):
+    """Blocked rates (zero padding) from [C][P] arrays (host or device)."""
+    kc = Kc.detach().cpu().numpy() if isinstance(Kc, torch.Tensor) else np.asarray(Kc)
+    kf = Kf.detach().cpu().numpy() if isinstance(Kf, torch.Tensor) else np.asarray(Kf)
+    C, P = kc.shape
+    N = int(round((np.sqrt(8 * P + 1) - 1) / 2))
+    f32 = dtype == torch.float32
+    nb = (C + 15) // 16
+    idx = _blocked_index(N, f32)
+    flat = np.zeros((nb, 64 * pair_slots(N)), np.float32 if f32 else np.float64)
+    pad = lambda a: np.concatenate([a, np.zeros((nb * 16 - C, P))]).reshape(nb, 16, P)
+    flat[:, idx] = pad(kc).transpose(0, 2, 1)
+    flat[:, idx + 1] = pad(kf).transpose(0, 2, 1)
+    return torch.as_tensor(flat.reshape(nb, pair_slots(N), 64), device=device)

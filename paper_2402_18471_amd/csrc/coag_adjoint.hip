@@ -369,22 +369,42 @@ __global__ __launch_bounds__(kBBlock) void k_adj_batch(Tables T, BatchTables B, 
             }
         };
         load_block(colq);
-        // the batch's blocked arrays: uniform bases, 32-bit lane offsets
-        // (pair p of cell cl at p * 16 + cl)
+        // the batch's arrays from uniform bases with 32-bit lane offsets: the
+        // rates in the blocked layout of coag_rates_blocked (blk_elem; one
+        // 16-byte load per pair in FP64, per two pairs in FP32), the
+        // derivative factors [P][16] (pair p of cell cl at p * 16 + cl)
         const long kbase = cell0 * P;
-        const RT *Kc = (const RT *)a.Kc + kbase, *Kf = (const RT *)a.Kf + kbase;
+        const RT *Kb = (const RT *)a.Kc + cell0 / kBC * 64 * pair_slot0(N);
+        const __amdgpu_buffer_rsrc_t kr =
+            raw_buffer(Kb, (unsigned)(64 * pair_slot0(N) * sizeof(RT)));
         const GT *Zp = (const GT *)a.Z + kbase, *Xp = (const GT *)a.X + kbase;
         const GT *Wp = VI ? (const GT *)a.W + kbase : nullptr;
         RT rc[kRingA][4], rf[kRingA][4];
         GT ez[kRingA][4], ex[kRingA][4], ew[kRingA][VI ? 4 : 1];
         auto load_k = [&](int i, int q, int u) {
             const int prow = i * (i + 1) / 2;
+            const unsigned s0 = (unsigned)pair_slot0(i);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int j = 16 * q + pj(r);
-                const unsigned o = (unsigned)(prow + (j <= i ? j : i)) * 16u + (unsigned)cl;
-                rc[u][r] = Kc[o];
-                rf[u][r] = Kf[o];
+                const int j = 16 * q + pj(r), jc = j <= i ? j : i;
+                const unsigned o = (unsigned)(prow + jc) * 16u + (unsigned)cl;
+                if constexpr (sizeof(RT) == 8) {
+                    const unsigned ob =
+                        (unsigned)blk_elem<double>(s0 + (jc >> 1), jc & 1, cl, 0) * 8u;
+                    const f64x2 v = buf_f64x2<false>(kr, ob);
+                    rc[u][r] = v[0];
+                    rf[u][r] = v[1];
+                } else if ((r & 1) == 0) {
+                    // pairs 4g + r, 4g + r + 1 (r even) from one slot; pairs
+                    // past the diagonal are masked where they are used
+                    const unsigned ob =
+                        (unsigned)blk_elem<float>(s0 + (jc >> 1), 0, cl, 0) * 4u;
+                    const f32x4 v = buf_f32x4<false>(kr, ob);
+                    rc[u][r] = v[0];
+                    rf[u][r] = v[1];
+                    rc[u][r + 1] = v[2];
+                    rf[u][r + 1] = v[3];
+                }
                 ez[u][r] = Zp[o];
                 ex[u][r] = Xp[o];
                 if (VI) ew[u][VI ? r : 0] = Wp[o];

@@ -272,17 +272,16 @@ int coag_rates(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *
 }
 
 int coag_rates_blocked(coag_ctx *ctx, int64_t C, const coag_cells *cells, const double *v_dust,
-                       const double *v_frag, int32_t f32, void *Kc, void *Kf, void *stream) {
+                       const double *v_frag, int32_t f32, void *K, void *stream) {
     if (!ctx) return fail(nullptr, COAG_EINVAL, "coag_rates_blocked: ctx is NULL");
     if (C < 0 || C > 0x7fffffff)
         return fail(ctx, COAG_EINVAL, "coag_rates_blocked: bad C = %lld", (long long)C);
     if (f32 != 0 && f32 != 1) return fail(ctx, COAG_EINVAL, "coag_rates_blocked: f32 must be 0 or 1");
     if (C == 0) return COAG_OK;
     if (int r = check_cells(ctx, cells)) return r;
-    if (!v_dust || !v_frag || !Kc || !Kf)
-        return fail(ctx, COAG_EINVAL, "coag_rates_blocked: NULL array");
+    if (!v_dust || !v_frag || !K) return fail(ctx, COAG_EINVAL, "coag_rates_blocked: NULL array");
     if (int r = set_device(ctx)) return r;
-    HIP_TRY(ctx, launch_rates_blocked(ctx->T, C, cell_arrays(cells), v_dust, v_frag, f32, Kc, Kf,
+    HIP_TRY(ctx, launch_rates_blocked(ctx->T, C, cell_arrays(cells), v_dust, v_frag, f32, K,
                                       (hipStream_t)stream));
     return COAG_OK;
 }
@@ -310,8 +309,13 @@ static int step_impl(const char *fn, coag_ctx *ctx, int64_t C, double *rho, cons
     if (!ctx) return fail(nullptr, COAG_EINVAL, "%s: ctx is NULL", fn);
     if (C < 0 || C > 0x7fffffff) return fail(ctx, COAG_EINVAL, "%s: bad C = %lld", fn, (long long)C);
     if (!tol) return fail(ctx, COAG_EINVAL, "%s: tol is NULL", fn);
-    if (C > 0 && (!rho || !Kc || !Kf || !nsub || !status))
-        return fail(ctx, COAG_EINVAL, "%s: rho, Kc, Kf, nsub and status are required", fn);
+    const bool blocked = tol->rates_layout != COAG_RATES_CP64;
+    if (C > 0 && (!rho || !Kc || (!blocked && !Kf) || !nsub || !status))
+        return fail(ctx, COAG_EINVAL, "%s: rho, Kc, Kf ([C][P] rates), nsub and status are "
+                    "required", fn);
+    if (blocked && Kf)
+        return fail(ctx, COAG_EINVAL, "%s: blocked rates hold both kinds in Kc; Kf must be NULL",
+                    fn);
     if (!(dt > 0.0) || !isfinite(dt)) return fail(ctx, COAG_EINVAL, "%s: dt must be > 0", fn);
     if (tol->mode < COAG_ADAPTIVE || tol->mode > COAG_REPLAY)
         return fail(ctx, COAG_EINVAL, "%s: unknown mode %d", fn, tol->mode);
@@ -406,7 +410,7 @@ int coag_step_noalloc(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, con
 // replay's step starts Ys and stage states Zs, the replay's state, slopes and
 // status, and v3.  (Zf, Xf: the rate-derivative factors Z, X.)
 struct AdjWs {
-    size_t Kc, Kf, Zf, Xf, Wf, Ys, Zs, y, slopes, status, v3, total;
+    size_t K, Zf, Xf, Wf, Ys, Zs, y, slopes, status, v3, total;
 };
 
 static AdjWs adj_ws(int N, size_t P, long S, int L, int split, int gf32, bool vertical) {
@@ -415,8 +419,7 @@ static AdjWs adj_ws(int N, size_t P, long S, int L, int split, int gf32, bool ve
     AdjWs w;
     size_t o = 0;
     auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
-    w.Kc = take(rt * P * Sb);
-    w.Kf = take(rt * P * Sb);
+    w.K = take(rt * 64 * (size_t)pair_slot0(N) * (Sb / kBatchCells));   // blocked, both kinds
     w.Zf = take(gt * P * Sb);
     w.Xf = take(gt * P * Sb);
     w.Wf = vertical ? take(gt * P * Sb) : 0;
@@ -495,8 +498,7 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
             const CellArrays cs{ca.T + s0, ca.rho_g + s0, ca.c_s + s0, ca.Omega + s0,
                                 ca.H + s0, ca.nu_mol + s0, ca.alpha + s0};
             const double *vd = v_dust + (size_t)s0 * N * 3, *vf = v_frag + s0;
-            HIP_TRY(ctx, launch_rates_blocked(ctx->T, Cs, cs, vd, vf, split ? 1 : 0, b + w.Kc,
-                                              b + w.Kf, st));
+            HIP_TRY(ctx, launch_rates_blocked(ctx->T, Cs, cs, vd, vf, split ? 1 : 0, b + w.K, st));
             HIP_TRY(ctx, launch_rate_derivs_blocked(ctx->T, Cs, cs, vd, vf, gf32, b + w.Zf,
                                                     b + w.Xf, ctx->T.vertical ? b + w.Wf : nullptr,
                                                     st));
@@ -505,8 +507,8 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
                                         hipMemcpyDeviceToDevice, st));
             StepArgs sa;
             sa.rho = y;
-            sa.Kc = (const double *)(b + w.Kc);
-            sa.Kf = (const double *)(b + w.Kf);
+            sa.Kc = (const double *)(b + w.K);
+            sa.Kf = nullptr;
             sa.dt = 0.0;
             sa.h = nullptr;
             sa.rtol = sa.atol_rel = sa.h_min_rel = 0.0;
@@ -523,8 +525,8 @@ int coag_step_backward(coag_ctx *ctx, int64_t C, const double *rho_in, const coa
                                            split ? COAG_RATES_BLK32 : COAG_RATES_BLK64,
                                            (double *)(b + w.slopes), st));
             AdjBatchArgs aa;
-            aa.Kc = b + w.Kc;
-            aa.Kf = b + w.Kf;
+            aa.Kc = b + w.K;
+            aa.Kf = nullptr;
             aa.Z = b + w.Zf;
             aa.X = b + w.Xf;
             aa.W = ctx->T.vertical ? b + w.Wf : nullptr;

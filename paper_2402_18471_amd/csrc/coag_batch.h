@@ -64,7 +64,7 @@ size_t batch_ws_bytes(int N, long C, int prec, int layout);
 // Zs hold the forward replay's step starts and stage states (layout of
 // AdjArgs, stride L = log_stride).
 struct AdjBatchArgs {
-    const void *Kc, *Kf;                 // [ceil(C/16)][P][16] RT
+    const void *Kc, *Kf;                 // Kc: the blocked rates (blk_elem), RT; Kf unused
     const void *Z, *X;                   // [ceil(C/16)][P][16] GT
     const void *W;                       // the same, vertically integrated kernel only
     const double *v_frag;                // [C]

@@ -205,14 +205,14 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
     auto wsp = [&](int c, int v) { return ws + ((cell0 + c) * 5 + v) * (long)N; };
 
     // ---- FP64 form fed [C][P] rates: the batch's rates, reordered once per
-    // call: pair-major, then kind (Kc, Kf), then the 16 cells, so that every
-    // right-hand side streams whole cache lines (rows of [C][P] are P elements
-    // apart).  Staged through LDS tiles of TP pairs (rows padded by one element
-    // against bank conflicts).  Fed the 16-cell-blocked rates of
-    // coag_rates_blocked (BLK), both forms read them in place: a 128-byte line
-    // (FP64) or 64-byte run (FP32) per pair; the split form reads FP64 [C][P]
-    // rates directly.
-    RT *const kb = wk + bt * P * 2 * kBC;
+    // call into the blocked layout of coag_rates_blocked (blk_elem), so that
+    // every right-hand side streams whole cache lines (rows of [C][P] are P
+    // elements apart).  Staged through LDS tiles of TP pairs (rows padded by
+    // one element against bank conflicts).  Fed the blocked rates (BLK), both
+    // forms read them in place, one 16-byte load per lane and pair (FP64) or
+    // pair of pairs (FP32); the split form reads FP64 [C][P] rates directly.
+    const long SL = pair_slot0(N);                  // pair slots per block
+    RT *const kb = wk + bt * 64 * SL;
     if (PREC == 0 && !BLK) {
         RT *tile = (RT *)lds;
         const int cap = (int)((3 * kBC * N * sizeof(double)) / (2 * kBC * sizeof(RT))) - 1;
@@ -227,8 +227,12 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             }
             __syncthreads();
             for (int t = threadIdx.x; t < 2 * kBC * np; t += kBBlock) {
-                const int r = t & 31, pp = t >> 5;          // r = kind * 16 + cell
-                kb[(p0 + pp) * 2 * kBC + r] = tile[r * TS + pp];
+                const int kind = t & 1, c = (t >> 1) & 15, pp = t >> 5;
+                const uint32_t ij = T.pij[p0 + pp];
+                const int i = pair_i(ij), j = pair_j(ij);
+                const long sl = pair_slot0(i) + (j >> 1);
+                kb[blk_elem<RT>(sl, j & 1, c, kind)] = tile[(kind * 16 + c) * TS + pp];
+                if (i == j && !(i & 1)) kb[blk_elem<RT>(sl, 1, c, kind)] = (RT)0;
             }
             __syncthreads();
         }
@@ -362,28 +366,25 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
             for (int r = 0; r < 4; ++r)
                 atomicAdd(&net[(g + 4 * r) * NS + bin], acc64[r] + acf64[r]);
         };
-        // the batch's rates: reordered in the workspace ([P][kind][16]), or the
-        // caller's 16-cell-blocked arrays ([P][16] per kind), read through
-        // raw buffers over the batch (byte offsets below 2^32 for N <= 1023)
-        const RT *kcb = BLK ? (const RT *)a.Kc + cell0 * P : kb;
-        const RT *kfb = BLK ? (const RT *)a.Kf + cell0 * P : kb + kBC;
-        constexpr unsigned kps = BLK ? kBC : 2 * kBC;
-        const unsigned span = (unsigned)((P * kps + kBC) * sizeof(RT));
-        const __amdgpu_buffer_rsrc_t kcr = raw_buffer(kcb, span), kfr = raw_buffer(kfb, span);
+        // the batch's rates: reordered in the workspace, or the caller's
+        // blocked array, both in the blocked layout, read through a raw buffer
+        // over the batch (byte offsets below 2^32 for N <= 1023)
+        const RT *kbb = BLK ? (const RT *)a.Kc + cell0 / kBC * 64 * SL : kb;
+        const __amdgpu_buffer_rsrc_t kr = raw_buffer(kbb, (unsigned)(64 * SL * sizeof(RT)));
         // lane (cell, g): pairs 16q + 4g + s, s = 0..3, both kinds
         double rkc[kRing64][4], rkf[kRing64][4], bb[2][8];
         auto load_k = [&](int i, int q, double (&kc)[4], double (&kf)[4]) {
-            const unsigned prow = (unsigned)(i * (i + 1) / 2);
+            const unsigned s0 = (unsigned)pair_slot0(i);
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const int j = 16 * q + 4 * g + s;
-                const unsigned o =
-                    ((prow + (unsigned)(j <= i ? j : i)) * kps + (unsigned)cl) * sizeof(RT);
+                const int j = 16 * q + 4 * g + s, jc = j <= i ? j : i;
+                const unsigned o = (unsigned)blk_elem<double>(s0 + (jc >> 1), jc & 1, cl, 0) * 8u;
                 // streaming loads: the rates are read once per right-hand
                 // side, and keeping them out of L2 leaves it to the D
                 // operands every batch shares (9 % less traffic, 2 % faster)
-                kc[s] = buf_f64<true>(kcr, o);
-                kf[s] = buf_f64<true>(kfr, o);
+                const f64x2 v = buf_f64x2<true>(kr, o);
+                kc[s] = v[0];
+                kf[s] = v[1];
             }
         };
         // the chunk's eight operands of this lane as four 16-byte loads, each
@@ -562,31 +563,43 @@ __global__ __launch_bounds__(kBBlock) void k_step_batch(Tables T, BatchTables B,
         // FP32 rates: pair p of the batch's cell cl at p * 16 + cl (padding
         // cells hold zeros); FP64 rates: [C][P], cells past C read cell C - 1
         constexpr bool blk = BLK;
-        constexpr unsigned ks = blk ? 16 : 1;
         const long cb = cell0 + cl < C ? cell0 + cl : C - 1;
         // blocked rates: the batch's uniform base and 32-bit lane offsets
         // (pair p of cell cl at p * 16 + cl); [C][P] rates: the lane's cell
-        // both from the batch's first cell: blocked, pair p of cell cl at
-        // p * 16 + cl; [C][P], at (cb - cell0) * P + p (cells past C read
-        // cell C - 1); byte offsets below 2^32 for N <= 1023
-        const long kbase = cell0 * P;
-        const unsigned kl = blk ? (unsigned)cl : (unsigned)((cb - cell0) * P);
-        const RT *Kc = (const RT *)a.Kc + kbase, *Kf = (const RT *)a.Kf + kbase;
+        // blocked FP32 rates: the batch's block of the caller's array (two
+        // pairs, both kinds, per 16-byte load); [C][P] FP64 rates: from the
+        // batch's first cell, cell cl at (cb - cell0) * P + p (cells past C
+        // read cell C - 1).  Byte offsets below 2^32 for N <= 1023.
+        const long SL = pair_slot0(N);
+        const unsigned kl = (unsigned)((cb - cell0) * P);
+        const RT *Kc = (const RT *)a.Kc + (blk ? cell0 / kBC * 64 * SL : cell0 * P);
+        const RT *Kf = blk ? Kc : (const RT *)a.Kf + cell0 * P;
         const long ncb = C - cell0 < kBC ? C - cell0 : kBC;
-        const unsigned span = (unsigned)((blk ? P * ks + kBC : ncb * P) * sizeof(RT));
+        const unsigned span = (unsigned)((blk ? 64 * SL : ncb * P) * sizeof(RT));
         const __amdgpu_buffer_rsrc_t kcr = raw_buffer(Kc, span), kfr = raw_buffer(Kf, span);
         RT rk[kRing16][8];
         uint4 bb[2][3];
         auto load_k = [&](int i, int q, RT (&k)[8]) {
-            const unsigned prow = (unsigned)(i * (i + 1) / 2);
+            if constexpr (blk) {
+                // pairs 4g + 2u, 4g + 2u + 1 (clamped to the row's last slot:
+                // pairs past the diagonal are masked where they are used)
+                const unsigned s0 = (unsigned)pair_slot0(i);
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int j = 16 * q + 4 * g + s;
-                const unsigned o = ((prow + (unsigned)(j <= i ? j : i)) * ks + kl) * sizeof(RT);
-                if constexpr (sizeof(RT) == 4) {
-                    k[s] = buf_f32<false>(kcr, o);
-                    k[4 + s] = buf_f32<false>(kfr, o);
-                } else {
+                for (int u = 0; u < 2; ++u) {
+                    const int j = 16 * q + 4 * g + 2 * u, jc = j <= i ? j : i;
+                    const unsigned o = (unsigned)blk_elem<float>(s0 + (jc >> 1), 0, cl, 0) * 4u;
+                    const f32x4 v = buf_f32x4<false>(kcr, o);
+                    k[2 * u] = v[0];
+                    k[4 + 2 * u] = v[1];
+                    k[2 * u + 1] = v[2];
+                    k[5 + 2 * u] = v[3];
+                }
+            } else {
+                const unsigned prow = (unsigned)(i * (i + 1) / 2);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int j = 16 * q + 4 * g + s;
+                    const unsigned o = (prow + (unsigned)(j <= i ? j : i) + kl) * 8u;
                     k[s] = buf_f64<false>(kcr, o);
                     k[4 + s] = buf_f64<false>(kfr, o);
                 }
@@ -945,9 +958,8 @@ static size_t slope_bytes(int N, long C) {
 
 size_t batch_ws_bytes(int N, long C, int prec, int layout) {
     const long nb = (C + kBC - 1) / kBC;
-    const size_t P = (size_t)N * (N + 1) / 2;
     const bool reorder = prec == 0 && layout == 0;
-    return slope_bytes(N, C) + (reorder ? (size_t)nb * P * 2 * kBC * sizeof(double) : 0);
+    return slope_bytes(N, C) + (reorder ? (size_t)nb * 64 * pair_slot0(N) * sizeof(double) : 0);
 }
 
 hipError_t launch_step_batch(const Tables &T, const BatchTables &B, long C, const StepArgs &a,

@@ -104,6 +104,18 @@ template <bool NT>
 __device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, unsigned off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, NT ? 2 : 0));
 }
+// 16 bytes at byte offset off, as two doubles or four floats (the whole
+// vector is cast: the compiler mistranslates element reads of the 128-bit
+// load's integer result)
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ f64x2 buf_f64x2(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, NT ? 2 : 0));
+}
+template <bool NT>
+__device__ __forceinline__ f32x4 buf_f32x4(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, NT ? 2 : 0));
+}
 
 // The batch a workgroup takes.  Workgroups are dealt to the eight XCDs in
 // turn (workgroup w to XCD w mod 8), and each XCD runs its share from its own

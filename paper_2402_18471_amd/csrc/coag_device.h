@@ -42,6 +42,25 @@ struct Tables {
     int vertical;          // 1: vertically integrated kernel (column densities)
 };
 
+// ---------------------------------------------------------------------------
+// The 16-cell-blocked rate layout (coag_rates_blocked): per block of 16 cells
+// the pairs of each row i are taken two by two, pair (i, j) in slot
+// pair_slot0(i) + j / 2 with parity j & 1 (a row of odd length, i even, ends
+// with a zero entry (i, i + 1)); pair_slot0(N) slots per block, 64 values per
+// slot (2 parities x 16 cells x 2 kinds, Kc then Kf), ordered so that one
+// 16-byte load per lane of a wave is contiguous:
+//   double: [slot][parity][cell][kind]     float: [slot][cell][parity][kind]
+// ---------------------------------------------------------------------------
+__host__ __device__ inline long pair_slot0(int i) {
+    const long m = i >> 1;
+    return (i & 1) ? (m + 1) * (m + 1) : m * (m + 1);
+}
+template <typename RT>
+__host__ __device__ inline long blk_elem(long slot, int parity, int cell, int kind) {
+    return sizeof(RT) == 8 ? ((slot * 2 + parity) * 16 + cell) * 2 + kind
+                           : ((slot * 16 + cell) * 2 + parity) * 2 + kind;
+}
+
 __device__ __forceinline__ int pair_i(uint32_t v) { return v & 1023u; }
 __device__ __forceinline__ int pair_j(uint32_t v) { return (v >> 10) & 1023u; }
 __device__ __forceinline__ int dst_c(uint32_t v) { return v & 1023u; }

@@ -204,14 +204,13 @@ template <int TAB, bool VI, typename OT>
 __global__ __launch_bounds__(1024) void k_rates_blk(Tables T, CellArrays cells,
                                                     const double *__restrict__ v_dust,
                                                     const double *__restrict__ v_frag,
-                                                    OT *__restrict__ Kc, OT *__restrict__ Kf,
-                                                    long C) {
+                                                    OT *__restrict__ K, long C) {
     extern __shared__ double lds[];
     const int P = T.P;
     const int p0 = (int)((long)P * blockIdx.y / gridDim.y);
     const int p1 = (int)((long)P * (blockIdx.y + 1) / gridDim.y);
-    rates_block<TAB, VI, 1024>(T, cells, v_dust, v_frag, Kc, Kf, C, (long)blockIdx.x * 16, p0,
-                               p1, lds);
+    rates_block<TAB, VI, 1024>(T, cells, v_dust, v_frag, K, C, (long)blockIdx.x * 16, p0, p1,
+                               lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -564,7 +563,7 @@ hipError_t launch_rates(const Tables &T, long C, const CellArrays &cells, const 
 
 template <typename OT>
 static hipError_t launch_rates_blk(const Tables &T, long C, const CellArrays &cells,
-                                   const double *v_dust, const double *v_frag, OT *Kc, OT *Kf,
+                                   const double *v_dust, const double *v_frag, OT *K,
                                    hipStream_t st) {
     const unsigned blocks = (unsigned)((C + 15) / 16);
     // few blocks (small grids of cells): share each block's pairs among
@@ -577,7 +576,7 @@ static hipError_t launch_rates_blk(const Tables &T, long C, const CellArrays &ce
         const size_t bytes = rates_blk_lds_bytes<TAB, VI>(T.N);                                   \
         if (hipError_t e = allow_lds(k_rates_blk<TAB, VI, OT>, bytes)) return e;                  \
         hipLaunchKernelGGL((k_rates_blk<TAB, VI, OT>), dim3(blocks, slices), dim3(1024), bytes,   \
-                           st, T, cells, v_dust, v_frag, Kc, Kf, C);                              \
+                           st, T, cells, v_dust, v_frag, K, C);                                   \
     }
     if (!vi) {
         if (tab == 7) RATES_BLK(7, false)
@@ -593,11 +592,11 @@ static hipError_t launch_rates_blk(const Tables &T, long C, const CellArrays &ce
 }
 
 hipError_t launch_rates_blocked(const Tables &T, long C, const CellArrays &cells,
-                                const double *v_dust, const double *v_frag, int f32, void *Kc,
-                                void *Kf, hipStream_t st) {
+                                const double *v_dust, const double *v_frag, int f32, void *K,
+                                hipStream_t st) {
     if (C == 0) return hipSuccess;
-    if (f32) return launch_rates_blk(T, C, cells, v_dust, v_frag, (float *)Kc, (float *)Kf, st);
-    return launch_rates_blk(T, C, cells, v_dust, v_frag, (double *)Kc, (double *)Kf, st);
+    if (f32) return launch_rates_blk(T, C, cells, v_dust, v_frag, (float *)K, st);
+    return launch_rates_blk(T, C, cells, v_dust, v_frag, (double *)K, st);
 }
 
 hipError_t launch_rhs(const Tables &T, long C, const double *rho, const double *Kc,

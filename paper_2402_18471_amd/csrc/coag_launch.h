@@ -49,10 +49,11 @@ hipError_t launch_build(int N, const double *m, const double *me, double eta, do
                         hipStream_t st);
 hipError_t launch_rates(const Tables &T, long C, const CellArrays &cells, const double *v_dust,
                         const double *v_frag, double *Kc, double *Kf, hipStream_t st);
-// rates in the 16-cell-blocked layout, float (f32) or double
+// rates in the 16-cell-blocked layout (blk_elem: both kinds in one array),
+// float (f32) or double
 hipError_t launch_rates_blocked(const Tables &T, long C, const CellArrays &cells,
-                                const double *v_dust, const double *v_frag, int f32, void *Kc,
-                                void *Kf, hipStream_t st);
+                                const double *v_dust, const double *v_frag, int f32, void *K,
+                                hipStream_t st);
 hipError_t launch_rhs(const Tables &T, long C, const double *rho, const double *Kc,
                       const double *Kf, double *out, hipStream_t st);
 size_t step_lds_bytes(int N);

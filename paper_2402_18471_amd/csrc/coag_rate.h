@@ -221,11 +221,11 @@ __device__ inline RateDerivs pair_rate_derivs(const CellRate &r, double alpha, d
 }
 
 // Pair rates of one block of 16 cells (cells cell0 .. cell0 + 15) in the
-// 16-cell-blocked layout (rate of cell c, pair p at ((c / 16) P + p) 16 +
-// c % 16; cells past C get zeros), double or rounded to float, by NT threads
-// of a workgroup: thread t works on cell t % 16 and pairs t / 16 + (NT / 16) k,
-// so that the 16 cells of a pair leave as one run (64 bytes in FP32, a
-// 128-byte line in FP64).  Per-grain values in `lds` as [bin][value][cell]
+// 16-cell-blocked layout (blk_elem; cells past C get zeros), double or
+// rounded to float, by NT threads of a workgroup: thread t works on cell
+// t % 16 and pairs t / 16 + (NT / 16) k, so that the 16 cells of a pair
+// leave together (256 contiguous bytes in FP64, 256 bytes in 16-byte steps
+// in FP32).  Per-grain values in `lds` as [bin][value][cell]
 // (the lanes of a pair read 16 consecutive doubles).  TAB = 7 tabulates St, A,
 // B, C and the velocity; for grids whose 16 cells' values would not fit LDS
 // otherwise, TAB = 6 leaves out C and TAB = 1 keeps St only (the velocity then
@@ -242,14 +242,13 @@ inline size_t rates_blk_lds_bytes(int N) {
 template <int TAB, bool VI, int NT, typename OT>
 __device__ void rates_block(const Tables &T, const CellArrays &cells,
                             const double *__restrict__ v_dust, const double *__restrict__ v_frag,
-                            OT *__restrict__ Kc, OT *__restrict__ Kf, long C, long cell0,
-                            int p0, int p1, double *lds) {
+                            OT *__restrict__ K, long C, long cell0, int p0, int p1, double *lds) {
     static_assert(TAB == 7 || TAB == 6 || TAB == 1, "tabulated values per grain");
     static_assert(NT % 64 == 0, "whole waves");
     constexpr int VX = TAB - 3;                       // first velocity row (TAB >= 6)
     constexpr int TW = TAB + (VI ? 1 : 0);            // values per grain; h^2 last
     constexpr int SLOTS = NT / 16;
-    const int N = T.N, P = T.P;
+    const int N = T.N;
     double *tb = lds, *sv = lds + 16 * TW * N, *imv = sv + N;
     // [bin][value][cell]: the values of one grain 128 bytes apart, so that
     // a lane reads them all from one address with immediate offsets
@@ -311,14 +310,18 @@ __device__ void rates_block(const Tables &T, const CellArrays &cells,
         g.s = sv[k];
         return g;
     };
-    OT *kc = Kc + cell0 * P + cl, *kf = Kf + cell0 * P + cl;
+    // the block's base; both kinds of a pair are one 16-byte (FP64) or
+    // 8-byte (FP32) store, and a row of odd length gets its zero entry with
+    // its diagonal pair
+    OT *kb = K + (cell0 / 16) * 64 * pair_slot0(N);
+    typedef OT OT2 __attribute__((ext_vector_type(2)));
     uint32_t ijn = p0 + slot < p1 ? T.pij[p0 + slot] : 0u;
     for (int p = p0 + slot; p < p1; p += SLOTS) {
         const uint32_t ij = ijn;
         if (p + SLOTS < p1) ijn = T.pij[p + SLOTS];
+        const int i = pair_i(ij), j = pair_j(ij);
         OT oc = (OT)0, of = (OT)0;
         if (live) {
-            const int i = pair_i(ij), j = pair_j(ij);
             Grain gi = grain(i);
             const double S = stir_s(r, gi.st);
             if (TAB == 6) gi.ct = gi.st * gi.st / (S + gi.st);
@@ -328,8 +331,9 @@ __device__ void rates_block(const Tables &T, const CellArrays &cells,
             oc = (OT)c64;
             of = (OT)f64;
         }
-        kc[(long)p * 16] = oc;
-        kf[(long)p * 16] = of;
+        const long sl = pair_slot0(i) + (j >> 1);
+        *(OT2 *)(kb + blk_elem<OT>(sl, j & 1, cl, 0)) = OT2{oc, of};
+        if (i == j && !(i & 1)) *(OT2 *)(kb + blk_elem<OT>(sl, 1, cl, 0)) = OT2{(OT)0, (OT)0};
     }
 }
 

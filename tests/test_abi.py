@@ -80,7 +80,7 @@ def test_calls_reject_null_context(L):
     assert lib.coag_step(None, 1, None, None, None, 1.0, None, ct.byref(tol), None, None, None,
                          None, None) == L.COAG_EINVAL
     assert lib.coag_rates(None, 1, None, None, None, None, None, None) == L.COAG_EINVAL
-    assert lib.coag_rates_blocked(None, 1, None, None, None, 1, None, None, None) == L.COAG_EINVAL
+    assert lib.coag_rates_blocked(None, 1, None, None, None, 1, None, None) == L.COAG_EINVAL
     assert lib.coag_step_backward(None, 1, None, None, None, None, None, 1, None, None, None,
                                   None, None, 0, None) == L.COAG_EINVAL
     lib.coag_destroy(None)

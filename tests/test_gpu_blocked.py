@@ -1,5 +1,5 @@
-"""16-cell-blocked FP64 rates (coag_rates_blocked, f32 = 0) and the batched
-FP64 step reading them.
+"""16-cell-blocked FP64 rates (coag_rates_blocked, f32 = 0: both kinds in one
+array, rows taken two pairs at a time) and the batched FP64 step reading them.
 
 The blocked writer runs the same per-pair arithmetic as coag_rates, so its
 values equal coag_rates' after unblocking (to 1e-15 relative, allowing a
@@ -54,8 +54,8 @@ def _case(name, n_r, n_z, n_bins=None, kernel=None):
 
 
 def _unblock(K, C):
-    x = _np(K).transpose(0, 2, 1).reshape(-1, K.shape[1])
-    return x[:C], x[C:]
+    from paper_2402_18471_amd.coag import unblock
+    return unblock(K, C)
 
 
 @pytest.mark.parametrize("case", [("disc256x128_n150", 5, 7, None), ("disc512x256_n200", 4, 4, None),
@@ -64,14 +64,17 @@ def test_blocked_f64_rates_equal_cp_rates(case):
     cfg, d, ctx, cells = _case(*case)
     C = cfg.n_cells
     vd, vf = _t(d["v_dust"]), _t(d["v_frag"])
+    from paper_2402_18471_amd.coag import pair_slots
     Kc, Kf = ctx.coag_rates(cells, vd, vf)
-    Bc, Bf = ctx.coag_rates_blocked(cells, vd, vf, dtype=torch.float64)
+    B = ctx.coag_rates_blocked(cells, vd, vf, dtype=torch.float64)
     torch.cuda.synchronize()
-    assert tuple(Bc.shape) == ((C + 15) // 16, ctx.P, 16)
-    for B, K in ((Bc, Kc), (Bf, Kf)):
-        x, pad = _unblock(B, C)
+    assert tuple(B.shape) == ((C + 15) // 16, pair_slots(cfg.n_bins), 64)
+    bc, bf, rest = _unblock(B, C)
+    for x, K in ((bc, Kc), (bf, Kf)):
         np.testing.assert_allclose(x, _np(K), rtol=1e-15, atol=0)
-        assert pad.shape[0] == (-C) % 16 and np.all(pad == 0.0)
+    # padding cells and the zero entries of rows of odd length
+    assert rest.size == 2 * ((-C) % 16) * ctx.P + 2 * 16 * ((cfg.n_bins + 1) // 2) * B.shape[0]
+    assert np.all(rest == 0.0)
 
 
 @pytest.mark.parametrize("case", [("disc256x128_n150", 5, 7), ("disc512x256_n200", 4, 4),
@@ -86,16 +89,15 @@ def test_step_with_blocked_f64_rates_matches_the_cp_step(case, mode):
     B = ctx.coag_rates_blocked(cells, vd, vf, dtype=torch.float64)
     # blocked rates hold the same values (within one rounding): step with
     # the [C][P] rates rebuilt from them, so both runs see identical numbers
-    x, _ = _unblock(B[0], C)
-    y, _ = _unblock(B[1], C)
+    x, y, _ = _unblock(B, C)
     K = (_t(x), _t(y))
     for dt in (d["dt"], 20 * d["dt"]):
         kw = dict(max_sub=256) if mode == "adaptive" else dict(
             mode=L.FIXED, nsub=torch.full((C,), 5, dtype=torch.int32, device=DEV), max_sub=8)
         a = ctx.coag_step(_t(d["rho"]), *K, dt, **{k: (v.clone() if torch.is_tensor(v) else v)
                                                     for k, v in kw.items()})
-        b = ctx.coag_step(_t(d["rho"]), *B, dt, **{k: (v.clone() if torch.is_tensor(v) else v)
-                                                    for k, v in kw.items()})
+        b = ctx.coag_step(_t(d["rho"]), B, None, dt, **{k: (v.clone() if torch.is_tensor(v) else v)
+                                                         for k, v in kw.items()})
         torch.cuda.synchronize()
         assert np.all(_np(a["status"]) == 0)
         for key in ("nsub", "nrej", "status"):
@@ -113,12 +115,14 @@ def test_blocked_f64_rate_errors():
     B = ctx.coag_rates_blocked(cells, vd, vf, dtype=torch.float64)
     rho = _t(d["rho"])
     with pytest.raises(L.CoagError) as e:               # double blocked rates, split step
-        ctx.coag_step(rho, *B, d["dt"], prec=1)
+        ctx.coag_step(rho, B, None, d["dt"], prec=1)
     assert e.value.code == L.COAG_EINVAL
+    with pytest.raises(ValueError):                     # blocked rates with a Kf
+        ctx.coag_step(rho, B, B, d["dt"])
     _, _, cctx, ccells = _case("disc64x32_n100", 2, 2, kernel="cell")
     B = cctx.coag_rates_blocked(ccells, vd, vf, dtype=torch.float64)
     with pytest.raises(L.CoagError) as e:               # per-cell FP64 kernel forced
-        cctx.coag_step(rho, *B, d["dt"])
+        cctx.coag_step(rho, B, None, d["dt"])
     assert e.value.code == L.COAG_ENOTSUP
     np.testing.assert_array_equal(_np(rho), d["rho"])   # untouched
     torch.cuda.synchronize()

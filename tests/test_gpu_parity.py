@@ -192,14 +192,10 @@ def test_batched_step_other_crater_yields(O, chi):
     C, n, dt = d["rho"].shape[0], 3, d["dt"] * 4
     rho0 = d["rho"]
 
-    def blocked(K):
-        # [C][P] -> [ceil(C/16)][P][16]: a layout only the batched kernel takes
-        # (COAG_ENOTSUP, raised, if this grid and chi did not allow it)
-        b = np.zeros((-(-C // 16) * 16, K.shape[1]))
-        b[:C] = K
-        return _t(b.reshape(-1, 16, K.shape[1]).transpose(0, 2, 1))
-
-    r = ctx.coag_step(_t(rho0), blocked(oKc), blocked(oKf), dt, mode=1,
+    from paper_2402_18471_amd.coag import block
+    # the blocked layout is one only the batched kernel takes (COAG_ENOTSUP,
+    # raised, if this grid and chi did not allow it)
+    r = ctx.coag_step(_t(rho0), block(oKc, oKf), None, dt, mode=1,
                       nsub=_t(np.full(C, n), torch.int32), max_sub=8)
     torch.cuda.synchronize()
     o = O.step(g, rho0, oKc, oKf, dt, mode=O.FIXED, nsub=n)

@@ -61,9 +61,10 @@ CASES = [("disc64x32_n100", 8, 4), ("disc256x128_n150", 8, 4), ("disc512x256_n20
 
 
 def _unblock(K, C):
-    """[ceil(C/16)][P][16] -> [C][P]; also returns the padding cells."""
-    x = _np(K).astype(np.float64).transpose(0, 2, 1).reshape(-1, K.shape[1])
-    return x[:C], x[C:]
+    """Blocked rates -> Kc, Kf [C][P] (float64), and the padding values."""
+    from paper_2402_18471_amd.coag import unblock
+    a, b, rest = unblock(K, C)
+    return a.astype(np.float64), b.astype(np.float64), rest
 
 
 # (13, 3) and (5, 7): a ragged last block of 16 cells.  The writer keeps
@@ -86,14 +87,15 @@ def test_rates_blocked_f32(O, case):
     else:
         cfg, g, d, ctx, cells = _case(O, *case)
     C = cfg.n_cells
-    Kc, Kf = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]))
+    from paper_2402_18471_amd.coag import pair_slots
+    K = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]))
     torch.cuda.synchronize()
-    assert tuple(Kc.shape) == ((C + 15) // 16, ctx.P, 16)
+    assert tuple(K.shape) == ((C + 15) // 16, pair_slots(cfg.n_bins), 64)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
-    for K, b in ((Kc, oKc), (Kf, oKf)):
-        a, pad = _unblock(K, C)
+    kc, kf, rest = _unblock(K, C)
+    for a, b in ((kc, oKc), (kf, oKf)):
         assert np.all(np.abs(a - b) <= 2.0 ** -24 * np.abs(b) + 1e-12 * (oKc + oKf))
-        assert pad.shape[0] == (-C) % 16 and np.all(pad == 0.0)
+    assert np.all(rest == 0.0)
 
 
 @pytest.mark.parametrize("rates", ["f64", "f32"])
@@ -102,7 +104,7 @@ def test_split_step_replays_oracle_steps(O, case, rates):
     cfg, g, d, ctx, cells = _case(O, *case)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
     if rates == "f32":
-        Kc, Kf = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]))
+        Kc, Kf = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"])), None
     else:
         Kc, Kf = _t(oKc), _t(oKf)
     for rho0, dt in ((d["rho"], d["dt"]), (d["rho"], 20 * d["dt"]),
@@ -129,7 +131,7 @@ def test_split_step_other_crater_yields(O, chi):
     g.chi = chi
     ctx = coag_create(ctx.m, ctx.m_edge, ctx.s, rho_m=cfg.rho_m, chi=chi)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
-    Kc, Kf = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]))
+    Kc, Kf = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"])), None
     for rho0, dt in ((d["rho"], 20 * d["dt"]), (_evolved(O, g, d, oKc, oKf), d["dt"])):
         o = O.step(g, rho0, oKc, oKf, dt, max_sub=512)
         assert np.all(o["status"] == 0)
@@ -148,7 +150,7 @@ def test_split_adaptive_replayed_by_oracle(O, case):
     """ADAPTIVE split step; the oracle replays its accepted steps."""
     cfg, g, d, ctx, cells = _case(O, *case)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
-    Kc, Kf = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]))
+    Kc, Kf = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"])), None
     rho0, dt = d["rho"], 20 * d["dt"]
     r = ctx.coag_step(_t(rho0), Kc, Kf, dt, prec=1, max_sub=256)
     torch.cuda.synchronize()
@@ -170,7 +172,7 @@ def test_split_rejections_and_host_errors(O):
     from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
     cfg, g, d, ctx, cells = _case(O, "disc64x32_n100", 2, 2)
     oKc, oKf = O.rates(g, d["cells"], d["v_dust"], d["v_frag"])
-    Kc32, Kf32 = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]))
+    Kc32, Kf32 = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"])), None
     rho = _t(d["rho"])
     before = rho.clone()
     with pytest.raises(L.CoagError) as e:       # FP32 rates with the FP64 step
@@ -223,7 +225,7 @@ def test_split_error_on_spread_sample(name):
         assert np.all(_np(r["status"]) == 0)
     rho0 = rho.clone()
     a = ctx.coag_step(rho0.clone(), *K64, 20 * d["dt"], max_sub=512)
-    b = ctx.coag_step(rho0.clone(), *K32, 20 * d["dt"], mode=L.REPLAY, prec=1,
+    b = ctx.coag_step(rho0.clone(), K32, None, 20 * d["dt"], mode=L.REPLAY, prec=1,
                       nsub=a["nsub"].clone(), h_log=a["h_log"])
     torch.cuda.synchronize()
     assert np.all(_np(a["status"]) == 0) and np.all(_np(b["status"]) == 0)

@@ -81,7 +81,8 @@ def _setup(O, name="col4096_n200", n_r=None, n_bins=None, kernel=None):
 
 
 def _unblock(K, C):
-    return _np(K).transpose(0, 2, 1).reshape(-1, K.shape[1])[:C]
+    from paper_2402_18471_amd.coag import unblock
+    return unblock(K, C)[:2]
 
 
 CASES = [("col0d_n200", None, None), ("col4096_n200", 40, None), ("col4096_n200", 37, 100)]
@@ -101,11 +102,10 @@ def test_vertical_rates_parity(O, case):
     torch.cuda.synchronize()
     for got, ora in ((_np(Kc), oKc), (_np(Kf), oKf)):
         assert np.all(np.abs(got - ora) <= 1e-12 * tot), np.max(np.abs(got - ora) / tot)
-    for B, ora in zip(B64, (oKc, oKf)):
-        x = _unblock(B, C)
+    for x, ora in zip(_unblock(B64, C), (oKc, oKf)):
         assert np.all(np.abs(x - ora) <= 1e-12 * tot), np.max(np.abs(x - ora) / tot)
-    for B, ora in zip(B32, (oKc, oKf)):
-        x = _unblock(B, C).astype(np.float64)
+    for x, ora in zip(_unblock(B32, C), (oKc, oKf)):
+        x = x.astype(np.float64)
         assert np.all(np.abs(x - ora) <= 1.2e-7 * np.abs(ora) + 1.2e-38)
 
 
@@ -179,7 +179,7 @@ def test_vertical_columns_adaptive_and_split(O):
     assert np.all(np.abs(_np(r["rho"]) - ld) <= 0.05 * base)
     # split precision, blocked FP32 rates
     B32 = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]), dtype=torch.float32)
-    rs = ctx.coag_step(_t(rho0), *B32, dt, mode=2, prec=1, nsub=_t(a["nsub"], torch.int32),
+    rs = ctx.coag_step(_t(rho0), B32, None, dt, mode=2, prec=1, nsub=_t(a["nsub"], torch.int32),
                        h_log=_t(a["h_log"]), max_sub=256)
     torch.cuda.synchronize()
     y, o = _np(rs["rho"]), a["rho"]

@@ -67,8 +67,8 @@ def test_noalloc_step_matches_the_step_twice(form):
         if form == "fp64_cp":
             rates = ctx.coag_rates(cells, vd, vf)
         else:
-            rates = ctx.coag_rates_blocked(
-                cells, vd, vf, dtype=torch.float32 if form == "split" else torch.float64)
+            rates = (ctx.coag_rates_blocked(
+                cells, vd, vf, dtype=torch.float32 if form == "split" else torch.float64), None)
         C = cfg.n_cells
         a, b = _pair(ctx, d, rates, L.FIXED, prec, nsub=torch.full((C,), 3, dtype=torch.int32,
                                                                      device=DEV), max_sub=3)
@@ -85,8 +85,9 @@ def test_noalloc_step_matches_the_step_twice(form):
 
 
 def test_noalloc_step_refuses_calls_beyond_the_scratch():
-    """[C][P] FP64 rates on 250 cells of 200 bins need 16 P + 40 N bytes per
-    cell (the step reorders the rates there): 82 MB, beyond the 64 MiB array."""
+    """[C][P] FP64 rates on 250 cells of 200 bins need 4 S(N) + 40 N (about
+    16 P + 48 N) bytes per cell (the step reorders the rates there): 82 MB,
+    beyond the 64 MiB array."""
     from paper_2402_18471_amd import _lib as L
     cfg, d, ctx = _disc(25, 10, 200)
     cells = {k: _t(v) for k, v in d["cells"].items()}
@@ -99,7 +100,7 @@ def test_noalloc_step_refuses_calls_beyond_the_scratch():
     torch.cuda.synchronize()
     assert torch.equal(rho, before)
     # the same cells with blocked rates fit (40 N bytes per cell) and match coag_step
-    K = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]), dtype=torch.float64)
+    K = ctx.coag_rates_blocked(cells, _t(d["v_dust"]), _t(d["v_frag"]), dtype=torch.float64), None
     a, b = _pair(ctx, d, K, L.FIXED, L.PREC_FP64,
                  nsub=torch.full((cfg.n_cells,), 2, dtype=torch.int32, device=DEV), max_sub=2)
     _same(a, b)
