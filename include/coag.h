@@ -254,7 +254,7 @@ int coag_step(coag_ctx *ctx, int64_t C, double *rho, const void *Kc, const void 
    array that the library holds on each device from its load to the end of
    the process, instead of the context's workspace.  That is room for
    40 N bytes per cell with blocked rates (COAG_RATES_BLK32 / BLK64: e.g. 8388
-   cells of 200 bins), and 4 S(N) + 40 N (about 16 P + 48 N) bytes per cell
+   cells of 200 bins), and 32 S(N) + 40 N (about 16 P + 48 N) bytes per cell
    with [C][P] FP64 rates in the FP64 step, which reorders them there (about
    200 cells of 200 bins).  Larger calls return COAG_EINVAL and launch nothing; split them
    into smaller ones.  Every call on one device shares that device's array:

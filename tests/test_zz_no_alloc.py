@@ -85,7 +85,7 @@ def test_noalloc_step_matches_the_step_twice(form):
 
 
 def test_noalloc_step_refuses_calls_beyond_the_scratch():
-    """[C][P] FP64 rates on 250 cells of 200 bins need 4 S(N) + 40 N (about
+    """[C][P] FP64 rates on 250 cells of 200 bins need 32 S(N) + 40 N (about
     16 P + 48 N) bytes per cell (the step reorders the rates there): 82 MB,
     beyond the 64 MiB array."""
     from paper_2402_18471_amd import _lib as L
