@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-vertical", action="store_true")
+    ap.add_argument("--no-transport", action="store_true")
     ap.add_argument("--cpu-sample-cells", type=int, default=512)
     ap.add_argument("--kernel", choices=("batch", "cell"), default="batch",
                     help="FP64 step kernel (cell: one workgroup per cell)")
@@ -608,6 +609,60 @@ def vertical_columns(torch, workload, steps=10, warmup=2):
     return out
 
 
+def transport_leg(torch, config, steps=20, warmup=3, evolve_steps=40):
+    """The transport step of the dynamics solver on `config`'s grid and
+    species (Sec. 3): `steps` CFL steps from the disc's initial state, each
+    step's two kernels timed with HIP events on the current stream; HBM
+    roofline of the step with 160 algorithmic bytes per (cell, species) (the
+    state at t^n read twice, the half-step state written once and read once,
+    the new state written: 5 x 32 bytes); then the scheduler (coag_evolve,
+    FP64 coagulation) over `evolve_steps` CFL steps of the same state."""
+    from paper_2402_18471_amd import disc
+    from paper_2402_18471_amd.coag import TransportContext, coag_create, coag_mass_grid
+    cfg = disc.CONFIGS[config]
+    m, me, s = coag_mass_grid(cfg.n_bins, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
+    d = disc.make_transport(cfg, s)
+    dev = "cuda:0"
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    tc = TransportContext(d["R_edge"], d["t_edge"], s, rho_m=cfg.rho_m, GM=d["GM"])
+    cells = {k: t(v) for k, v in d["cells"].items()}
+    rho, v, vg = t(d["rho"]), t(d["v"]), t(d["v_gas"])
+    C, N = cfg.n_cells, cfg.n_bins
+    ms, dts = [], []
+    for k in range(warmup + steps):
+        dt = tc.dt(cells, v)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tc.step(cells, vg, rho, v, dt)
+        e1.record()
+        e1.synchronize()
+        if k >= warmup:
+            ms.append(e0.elapsed_time(e1))
+            dts.append(dt)
+    step_ms = float(np.mean(ms))
+    byts = 160.0 * C * N
+    out = {"workload": f"{config} transport", "cells": C, "species": N, "steps": steps,
+           "step_ms": step_ms, "cell_species_updates_per_s": C * N / (step_ms * 1e-3),
+           "cfl_dt_yr": float(np.mean(dts)) / 3.15576e7,
+           "roofline": {"bound": "hbm", "achieved": byts / (step_ms * 1e-3) / 1e9, "peak": 8000.0,
+                        "unit": "GB/s", "frac": byts / (step_ms * 1e-3) / 1e9 / 8000.0,
+                        "algorithmic_bytes": "160 B per (cell, species) per step"}}
+    ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
+    rho, v = t(d["rho"]), t(d["v"])
+    h = torch.zeros(C, dtype=torch.float64, device=dev)
+    vf = t(d["v_frag"])
+    t_end = evolve_steps * tc.dt(cells, v)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    st = tc.evolve(ctx, cells, vg, vf, rho, v, h, t_end)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    out["evolve"] = {"t_end_yr": t_end / 3.15576e7, "wall_s": wall, **st,
+                     "note": "coag_evolve: CFL transport steps, FP64 coagulation triggered by the "
+                             "scheduler rule; wall time includes one host sync per transport step"}
+    return out
+
+
 def main():
     args = parse()
     if args.summarize_counters:
@@ -696,6 +751,9 @@ def main():
     if not args.no_vertical:
         out["vertical"] = vertical_columns(torch, "col4096_n200")
         progress("vertically integrated kernel timed on 4096 columns")
+    if not args.no_transport:
+        out["transport"] = transport_leg(torch, args.config)
+        progress("transport step and scheduler timed")
     if not args.no_cpu_baseline:
         progress("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(D.cfg, disc, args.cpu_sample_cells)

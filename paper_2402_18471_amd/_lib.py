@@ -14,6 +14,7 @@ import re
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libcoag.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "coag.h")
+HEADERS = [HEADER, os.path.join(os.path.dirname(HERE), "include", "coag_transport.h")]
 
 COAG_OK, COAG_EINVAL, COAG_ENOMEM, COAG_EHIP, COAG_ENOTSUP = 0, -1, -2, -3, -4
 CELL_OK, CELL_HMIN, CELL_MAXSUB, CELL_NONFINITE = 0, 1, 2, 3
@@ -40,6 +41,17 @@ class Tol(ct.Structure):
     _fields_ = [("rtol", ct.c_double), ("atol_rel", ct.c_double), ("h_min_rel", ct.c_double),
                 ("max_sub", ct.c_int32), ("mode", ct.c_int32), ("prec", ct.c_int32),
                 ("renorm", ct.c_int32), ("rates_layout", ct.c_int32)]
+
+
+class TGrid(ct.Structure):
+    _fields_ = [("n_r", ct.c_int32), ("n_z", ct.c_int32), ("R_edge", _dp), ("t_edge", _dp),
+                ("GM", ct.c_double), ("Sc", ct.c_double), ("c_adv", ct.c_double),
+                ("c_diff", ct.c_double)]
+
+
+class EvolveStats(ct.Structure):
+    _fields_ = [("transport_steps", ct.c_int64), ("coag_calls", ct.c_int64),
+                ("t_reached", ct.c_double), ("cells_failed", ct.c_int32)]
 
 
 class CoagError(RuntimeError):
@@ -76,6 +88,13 @@ def load():
                                          _vp, _vp, _vp, _vp]),
         "coag_step_backward": (ct.c_int, [_vp, i64, _vp, P(Cells), _vp, _vp, _vp, i32, _vp, _vp,
                                           _vp, _vp, _vp, i32, _vp]),
+        "coag_transport_create": (ct.c_int, [P(TGrid), i32, _dp, ct.c_double, P(_vp)]),
+        "coag_transport_destroy": (None, [_vp]),
+        "coag_transport_last_error": (ct.c_char_p, [_vp]),
+        "coag_transport_dt": (ct.c_int, [_vp, P(Cells), _vp, P(ct.c_double), _vp]),
+        "coag_transport_step": (ct.c_int, [_vp, P(Cells), _vp, _vp, _vp, ct.c_double, _vp]),
+        "coag_evolve": (ct.c_int, [_vp, _vp, i64, P(Cells), _vp, _vp, _vp, _vp, _vp, ct.c_double,
+                                   i64, P(Tol), P(EvolveStats), _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -85,10 +104,12 @@ def load():
 
 
 def header_symbols():
-    """Function names declared in include/coag.h."""
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(coag_[a-z0-9_]+)\s*\(", src)))
+    """Function names declared in include/coag.h and include/coag_transport.h."""
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(coag_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 class CoagCellError(CoagError):
@@ -113,4 +134,11 @@ def check_cells(status):
 def check(rc, ctx=None):
     if rc != COAG_OK:
         msg = load().coag_last_error(ctx)
+        raise CoagError(rc, msg.decode() if msg else "")
+
+
+def check_t(rc, tctx=None):
+    """check() for the transport calls (their messages live in the transport context)."""
+    if rc != COAG_OK:
+        msg = load().coag_transport_last_error(tctx)
         raise CoagError(rc, msg.decode() if msg else "")

@@ -9,14 +9,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcoag.so")
 SOURCES = ["coag_api.hip", "coag_kernels.hip", "coag_step2.hip", "coag_batch.hip",
-           "coag_adjoint.hip"]
+           "coag_adjoint.hip", "coag_transport.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-fno-fast-math", "-ffp-contract=fast", "-Wall", "-Wno-unused-function",
+    # fused multiply-adds wherever the source allows them, except in the
+    # functions that ask for none with `#pragma clang fp contract(off)`
+    # (plain -ffp-contract=fast would ignore those pragmas)
+    "-fno-fast-math", "-ffp-contract=fast-honor-pragmas", "-Wall", "-Wno-unused-function",
 ]
 
 

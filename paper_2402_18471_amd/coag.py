@@ -260,3 +260,77 @@ def block(Kc, Kf, dtype=torch.float64, device="cuda:0"):
     flat[:, idx] = pad(kc).transpose(0, 2, 1)
     flat[:, idx + 1] = pad(kf).transpose(0, 2, 1)
     return torch.as_tensor(flat.reshape(nb, pair_slots(N), 64), device=device)
+
+
+class TransportContext:
+    """coag_transport_create / destroy (include/coag_transport.h): the dust
+    transport step of the dynamics solver on an (R, t = Z/R) grid of n_r x n_z
+    cells for the N species of radii s, and the scheduler coupling it to a
+    CoagContext.  Marshalling only: the step runs in the library's kernels."""
+
+    def __init__(self, R_edge, t_edge, s, rho_m=1.67, GM=0.0, Sc=1.0, c_adv=0.4, c_diff=0.2):
+        self.R_edge = np.ascontiguousarray(R_edge, dtype=np.float64)
+        self.t_edge = np.ascontiguousarray(t_edge, dtype=np.float64)
+        self.s = np.ascontiguousarray(s, dtype=np.float64)
+        self.n_r, self.n_z, self.N = len(self.R_edge) - 1, len(self.t_edge) - 1, len(self.s)
+        self.C = self.n_r * self.n_z
+        dp = lambda a: a.ctypes.data_as(L._dp)
+        g = L.TGrid(self.n_r, self.n_z, dp(self.R_edge), dp(self.t_edge), GM, Sc, c_adv, c_diff)
+        h = ct.c_void_p()
+        self._lib = L.load()
+        L.check_t(self._lib.coag_transport_create(ct.byref(g), self.N, dp(self.s), rho_m,
+                                                   ct.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.coag_transport_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _cells(self, cells):
+        arrs = [_dev(cells[k], shape=(self.C,), name=k) for k in CELL_KEYS]
+        return L.Cells(*[a.data_ptr() for a in arrs]), arrs
+
+    def dt(self, cells, v):
+        """CFL time step (a host float; synchronises the current stream)."""
+        cs, keep = self._cells(cells)
+        _dev(v, shape=(self.C, self.N, 3), name="v")
+        out = ct.c_double()
+        L.check_t(self._lib.coag_transport_dt(self._h, ct.byref(cs), _ptr(v), ct.byref(out),
+                                               _stream()), self._h)
+        return out.value
+
+    def step(self, cells, v_gas, rho, v, dt):
+        """One transport step of dt in place on rho [C][N] and v [C][N][3]."""
+        cs, keep = self._cells(cells)
+        _dev(v_gas, shape=(self.C, 3), name="v_gas")
+        _dev(rho, shape=(self.C, self.N), name="rho")
+        _dev(v, shape=(self.C, self.N, 3), name="v")
+        L.check_t(self._lib.coag_transport_step(self._h, ct.byref(cs), _ptr(v_gas), _ptr(rho),
+                                                 _ptr(v), float(dt), _stream()), self._h)
+
+    def evolve(self, ctx: "CoagContext", cells, v_gas, v_frag, rho, v, h, t_end, max_steps=1 << 40,
+               prec=L.PREC_FP64, rtol=1e-2, atol_rel=1e-10, h_min_rel=1e-12, max_sub=256):
+        """Transport steps at the CFL time step up to t_end, with the
+        coagulation update triggered by the scheduler rule; rho, v, h in
+        place.  Returns the scheduler statistics as a dict."""
+        cs, keep = self._cells(cells)
+        _dev(v_gas, shape=(self.C, 3), name="v_gas")
+        _dev(v_frag, shape=(self.C,), name="v_frag")
+        _dev(rho, shape=(self.C, self.N), name="rho")
+        _dev(v, shape=(self.C, self.N, 3), name="v")
+        _dev(h, shape=(self.C,), name="h")
+        tol = L.Tol(rtol, atol_rel, h_min_rel, max_sub, L.ADAPTIVE, prec, 0, 0)
+        st = L.EvolveStats()
+        L.check_t(self._lib.coag_evolve(ctx._h, self._h, self.C, ct.byref(cs), _ptr(v_gas),
+                                         _ptr(v_frag), _ptr(rho), _ptr(v), _ptr(h), float(t_end),
+                                         int(max_steps), ct.byref(tol), ct.byref(st), _stream()),
+                  self._h)
+        return {"transport_steps": st.transport_steps, "coag_calls": st.coag_calls,
+                "t_reached": st.t_reached, "cells_failed": st.cells_failed}

@@ -93,6 +93,11 @@ static int set_device(coag_ctx *ctx) {
     return COAG_OK;
 }
 
+// the bin count of a context, for the transport scheduler (coag_transport.hip)
+namespace coag {
+int ctx_bins(const ::coag_ctx *ctx) { return ctx->N; }
+}  // namespace coag
+
 extern "C" {
 
 int coag_mass_grid(int32_t n_bins, double lo, double hi, int32_t by_mass, double rho_m,

@@ -246,3 +246,49 @@ def make_columns(cfg: ColumnConfig, s):
     rho = np.ascontiguousarray(cfg.dust_to_gas * sigma_g[:, None] * shape[None, :])
     return dict(cells=cells, v_dust=v, v_frag=np.full(cfg.n_r, float(cfg.v_frag)), rho=rho,
                 dt=cfg.dt)
+
+
+# ---------------------------------------------------------------------------
+# Transport inputs: the disc's grid as cylinder and cone faces, gas velocity,
+# absolute dust velocities.
+# ---------------------------------------------------------------------------
+GM_SUN = G_GRAV * M_SUN
+
+
+def transport_grid(cfg: DiscConfig):
+    """Face positions of the disc's cells for the transport step: R_edge
+    [n_r + 1] at the geometric midpoints of the log-spaced centres (the end
+    faces one half-ratio out), t_edge [n_z + 1] = Z / R of the cone faces, from
+    the midplane to z_max_h H / R, so that the cell centres are those of
+    make_cells."""
+    R = np.geomspace(cfg.r_in_au, cfg.r_out_au, cfg.n_r) * AU
+    if cfg.n_r > 1:
+        q = np.sqrt(R[1] / R[0])
+        R_edge = np.concatenate([[R[0] / q], np.sqrt(R[:-1] * R[1:]), [R[-1] * q]])
+    else:
+        R_edge = np.array([R[0] / 1.01, R[0] * 1.01])
+    t_edge = np.linspace(0.0, cfg.z_max_h * cfg.h_over_r, cfg.n_z + 1)
+    return np.ascontiguousarray(R_edge), np.ascontiguousarray(t_edge)
+
+
+def make_transport(cfg: DiscConfig, s):
+    """make_disc plus what the transport step needs: R_edge, t_edge, GM, the
+    gas velocity [C][3] (at rest in R and Z, rotating at the sub-Keplerian
+    Omega R (1 - eta) of the disc's pressure gradient) and absolute dust
+    velocities [C][N][3] (v_phi = the midplane Keplerian speed plus the
+    stand-in lag of make_dust_velocities)."""
+    d = make_disc(cfg, s)
+    cells = d["cells"]
+    R, Z, H, c_s = cells["R"], cells["Z"], cells["H"], cells["c_s"]
+    v_k = np.sqrt(GM_SUN / R)
+    r_au = R / AU
+    dlnp = -2.5 + 10.0 * (5.0 / r_au) ** 10 + (Z / H) ** 2
+    eta = -0.5 * (c_s / v_k) ** 2 * dlnp
+    v_gas = np.zeros((cfg.n_cells, 3))
+    v_gas[:, 1] = cells["Omega"] * R * (1.0 - eta)
+    v = d["v_dust"].copy()
+    v[:, :, 1] += v_k[:, None]
+    R_edge, t_edge = transport_grid(cfg)
+    d.update(R_edge=R_edge, t_edge=t_edge, GM=GM_SUN, v_gas=np.ascontiguousarray(v_gas),
+             v=np.ascontiguousarray(v))
+    return d

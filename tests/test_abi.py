@@ -1,5 +1,5 @@
 """The C-ABI library without a GPU: it loads, exports every function that
-include/coag.h declares, builds the same mass grid as the oracle, and rejects
+include/coag.h and include/coag_transport.h declare, builds the same mass grid as the oracle, and rejects
 bad arguments on the host before any device work."""
 import ctypes as ct
 
@@ -18,7 +18,9 @@ def test_library_exports_every_declared_symbol(L):
     names = L.header_symbols()
     assert set(names) == {"coag_mass_grid", "coag_create", "coag_destroy", "coag_last_error",
                           "coag_rates", "coag_rates_blocked", "coag_rhs", "coag_step",
-                          "coag_step_noalloc", "coag_step_backward"}
+                          "coag_step_noalloc", "coag_step_backward", "coag_transport_create",
+                          "coag_transport_destroy", "coag_transport_last_error",
+                          "coag_transport_dt", "coag_transport_step", "coag_evolve"}
     for n in names:
         assert hasattr(lib, n), n
 
@@ -91,3 +93,33 @@ def test_binding_refuses_host_tensors(L):
     from paper_2402_18471_amd.coag import _dev
     with pytest.raises(ValueError):
         _dev(torch.zeros(3, dtype=torch.float64))
+
+
+def test_transport_create_rejects_bad_grids_on_the_host(L):
+    """Every check of coag_transport_create runs before any device call."""
+    lib = L.load()
+    dp = lambda a: a.ctypes.data_as(L._dp)
+    R = np.array([1.0, 2.0, 3.0])
+    t = np.array([0.0, 0.1])
+    s = np.array([1e-4, 1e-3])
+    h = ct.c_void_p()
+
+    def create(R_, t_, s_=s, N=2, rho_m=1.6, GM=1.0, Sc=1.0, ca=0.4, cd=0.2, nr=None, nz=None):
+        g = L.TGrid(len(R_) - 1 if nr is None else nr, len(t_) - 1 if nz is None else nz,
+                    dp(R_), dp(t_), GM, Sc, ca, cd)
+        return lib.coag_transport_create(ct.byref(g), N, dp(s_), rho_m, ct.byref(h))
+
+    bad = [dict(R_=np.array([1.0, 1.0, 3.0]), t_=t),          # R not increasing
+           dict(R_=np.array([0.0, 1.0, 3.0]), t_=t),          # R_edge[0] = 0
+           dict(R_=R, t_=np.array([0.05, 0.1])),               # no midplane
+           dict(R_=R, t_=np.array([0.0, 0.0])),                # t not increasing
+           dict(R_=R, t_=t, s_=np.array([1e-4, 0.0])),         # a radius of 0
+           dict(R_=R, t_=t, N=0), dict(R_=R, t_=t, N=1024),
+           dict(R_=R, t_=t, rho_m=0.0), dict(R_=R, t_=t, GM=-1.0), dict(R_=R, t_=t, Sc=0.0),
+           dict(R_=R, t_=t, ca=0.0), dict(R_=R, t_=t, cd=-1.0), dict(R_=R, t_=t, nr=0),
+           dict(R_=R, t_=t, nz=0)]
+    for kw in bad:
+        assert create(**kw) == L.COAG_EINVAL, kw
+        assert h.value is None
+        assert lib.coag_transport_last_error(None).decode().startswith("coag_transport_create")
+    assert lib.coag_transport_create(None, 2, dp(s), 1.6, ct.byref(h)) == L.COAG_EINVAL

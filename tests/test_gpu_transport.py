@@ -1,0 +1,183 @@
+"""The transport step (coag_transport_dt / coag_transport_step) against the
+transport oracle on the same seeded disc inputs, and the scheduler
+(coag_evolve) against its rule, through the C ABI.
+
+Bars: the kernels and the oracle evaluate the same expressions in FP64 in
+different orders (per-cell sums of the four face fluxes, fused multiply-adds),
+so states agree to rounding: each (cell, species) density within 1e-12
+relative plus 1e-14 of its cell's largest density, each velocity within
+1e-12 relative plus 1e-12 of the largest speed of its cell and species row;
+the CFL step of the same velocities within 1e-14 relative.  The scheduler test runs the same library
+calls in Python by the rule of the header; the FP64 coagulation step deposits
+with LDS atomics whose order may differ between launches, so densities agree
+to 1e-12 relative (floor 1e-24 of the cell's mass) and the counts exactly.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _inputs(n_r, n_z, n_bins, fill=True):
+    from paper_2402_18471_amd import disc
+    cfg = disc.scaled(disc.CONFIGS["disc64x32_n100"], n_r, n_z, n_bins)
+    s = np.geomspace(cfg.s_min, cfg.s_max, n_bins)
+    d = disc.make_transport(cfg, s)
+    if fill:
+        # mass in every bin (the MRN start fills only the smallest grains)
+        d["rho"] = d["rho"] + 1e-3 * d["cells"]["rho_g"][:, None] * np.sqrt(s / s[-1])[None, :]
+    return cfg, s, d
+
+
+def _oracle(cfg, s, d):
+    from oracle import transport as T
+    g = T.geometry(d["R_edge"], d["t_edge"])
+    c = d["cells"]
+    sh = (cfg.n_r, cfg.n_z)
+    nu = c["alpha"] * c["c_s"] * c["H"]
+    gas = T.Gas(c["rho_g"].reshape(sh), c["c_s"].reshape(sh), nu.reshape(sh),
+                d["v_gas"].reshape(sh + (3,)), d["GM"])
+    return T, g, gas
+
+
+def _ctx(cfg, s, d):
+    from paper_2402_18471_amd.coag import TransportContext
+    return TransportContext(d["R_edge"], d["t_edge"], s, rho_m=cfg.rho_m, GM=d["GM"])
+
+
+def _close(rho_g, v_g, rho_o, v_o):
+    """the module docstring's bars; returns the largest ratios to them"""
+    C, N = rho_o.shape
+    rfloor = 1e-14 * np.abs(rho_o).max(axis=1, keepdims=True)
+    er = np.abs(rho_g - rho_o) / (1e-12 * np.abs(rho_o) + rfloor + 1e-300)
+    vmax = np.abs(v_o).max(axis=2, keepdims=True)
+    ev = np.abs(v_g - v_o) / (1e-12 * np.abs(v_o) + 1e-12 * vmax + 1e-300)
+    return float(er.max()), float(ev.max())
+
+
+@pytest.mark.parametrize("shape", [(24, 12, 12), (5, 3, 7), (1, 1, 4), (128, 64, 150)])
+def test_transport_steps_match_the_oracle(shape):
+    n_r, n_z, N = shape
+    cfg, s, d = _inputs(n_r, n_z, N)
+    T, g, gas = _oracle(cfg, s, d)
+    tc = _ctx(cfg, s, d)
+    cells = {k: _t(v) for k, v in d["cells"].items()}
+    rho, v, vg = _t(d["rho"]), _t(d["v"]), _t(d["v_gas"])
+    ro = d["rho"].reshape(n_r, n_z, N).copy()
+    vo = d["v"].reshape(n_r, n_z, N, 3).copy()
+    for k in range(2 if N > 100 else 3):
+        # the CFL rule on the same velocities (the GPU's): the same minimum
+        dt_g = tc.dt(cells, v)
+        dt_c = T.cfl_dt(g, gas, v.cpu().numpy().reshape(n_r, n_z, N, 3))
+        assert dt_g == pytest.approx(dt_c, rel=1e-14), (k, dt_g, dt_c)
+        # both sides step by the oracle's own step size
+        dt_o = T.cfl_dt(g, gas, vo)
+        tc.step(cells, vg, rho, v, dt_o)
+        ro, vo = T.step(g, gas, s, cfg.rho_m, ro, vo, dt_o)
+        torch.cuda.synchronize()
+        er, ev = _close(rho.cpu().numpy(), v.cpu().numpy().reshape(-1, N, 3),
+                        ro.reshape(-1, N), vo.reshape(-1, N, 3))
+        print(f"shape {shape} step {k}: density {er:.3g}, velocity {ev:.3g} of the bar")
+        assert er <= 1.0 and ev <= 1.0
+
+
+def test_transport_conserves_mass_on_the_gpu():
+    """Empty outer rings and top layers, as in the oracle's pin: the total
+    mass sum V rho over the disc stays constant to rounding."""
+    n_r, n_z, N = 40, 20, 10
+    cfg, s, d = _inputs(n_r, n_z, N)
+    rho = d["rho"].reshape(n_r, n_z, N)
+    # mass spreads by at most two cells a step
+    rho[:8] = rho[-8:] = 0.0
+    rho[:, -8:] = 0.0
+    T, g, gas = _oracle(cfg, s, d)
+    tc = _ctx(cfg, s, d)
+    cells = {k: _t(v) for k, v in d["cells"].items()}
+    rt, v, vg = _t(rho.reshape(-1, N)), _t(d["v"]), _t(d["v_gas"])
+    V = _t(g.V.reshape(-1, 1))
+    m0 = float((V * rt).sum())
+    for _ in range(3):
+        tc.step(cells, vg, rt, v, tc.dt(cells, v))
+    torch.cuda.synchronize()
+    r = rt.cpu().numpy().reshape(n_r, n_z, N)
+    assert np.all(r[0] == 0) and np.all(r[-1] == 0) and np.all(r[:, -1] == 0)
+    assert abs(float((V * rt).sum()) - m0) <= 1e-14 * m0
+
+
+def test_transport_rejects_bad_steps():
+    from paper_2402_18471_amd import _lib as L
+    cfg, s, d = _inputs(4, 3, 5)
+    tc = _ctx(cfg, s, d)
+    cells = {k: _t(v) for k, v in d["cells"].items()}
+    rho, v, vg = _t(d["rho"]), _t(d["v"]), _t(d["v_gas"])
+    before = rho.clone()
+    for dt in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(L.CoagError) as e:
+            tc.step(cells, vg, rho, v, dt)
+        assert e.value.code == L.COAG_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(rho, before)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split"])
+def test_evolve_follows_the_scheduler_rule(prec):
+    """coag_evolve against the rule written out with the library's own calls:
+    dt = CFL step clipped to what is left; transport step; when the time since
+    the last coagulation update reaches the smallest last sub-step of the
+    cells (0 at the start), or at t_end, rates and an ADAPTIVE step over that
+    time."""
+    from paper_2402_18471_amd import _lib as L
+    from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
+    n_r, n_z, N = 16, 8, 40
+    from paper_2402_18471_amd import disc
+    cfg = disc.scaled(disc.CONFIGS["disc64x32_n100"], n_r, n_z, N)
+    m, me, s = coag_mass_grid(N, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
+    d = disc.make_transport(cfg, s)
+    ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
+    tc = _ctx(cfg, s, d)
+    cells = {k: _t(v) for k, v in d["cells"].items()}
+    vg, vf = _t(d["v_gas"]), _t(d["v_frag"])
+    p = L.PREC_SPLIT_BF16 if prec == "split" else L.PREC_FP64
+    C = cfg.n_cells
+    # time: a few hundred CFL steps of the inner disc
+    dt0 = tc.dt(cells, _t(d["v"]))
+    t_end = 40.0 * dt0
+    rho_a, v_a, h_a = _t(d["rho"]), _t(d["v"]), torch.zeros(C, dtype=torch.float64, device=DEV)
+    st = tc.evolve(ctx, cells, vg, vf, rho_a, v_a, h_a, t_end, prec=p)
+    # the rule, step by step
+    rho_b, v_b, h_b = _t(d["rho"]), _t(d["v"]), torch.zeros(C, dtype=torch.float64, device=DEV)
+    t, since, trig, steps, calls = 0.0, 0.0, 0.0, 0, 0
+    dtype = torch.float32 if prec == "split" else torch.float64
+    while t < t_end:
+        dt = tc.dt(cells, v_b)
+        last = not (dt < t_end - t)
+        if last:
+            dt = t_end - t
+        tc.step(cells, vg, rho_b, v_b, dt)
+        steps += 1
+        t = t_end if last else t + dt
+        since += dt
+        if since >= trig or last:
+            K = ctx.coag_rates_blocked(cells, v_b, vf, dtype=dtype)
+            r = ctx.coag_step(rho_b, K, None, since, h=h_b, prec=p, max_sub=256)
+            calls += 1
+            since = 0.0
+            hp = h_b[h_b > 0]
+            trig = float(hp.min()) if hp.numel() else 0.0
+    torch.cuda.synchronize()
+    assert st["transport_steps"] == steps and st["coag_calls"] == calls, (st, steps, calls)
+    assert st["t_reached"] == t_end and st["cells_failed"] == 0
+    assert calls >= 2
+    a, b = rho_a.cpu().numpy(), rho_b.cpu().numpy()
+    M = b.sum(1, keepdims=True)
+    assert np.all(np.abs(a - b) <= 1e-12 * np.abs(b) + 1e-24 * M)
+    assert torch.allclose(v_a, v_b, rtol=1e-12, atol=0.0)
+    assert torch.allclose(h_a, h_b, rtol=1e-12, atol=0.0)
