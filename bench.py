@@ -609,14 +609,14 @@ def vertical_columns(torch, workload, steps=10, warmup=2):
     return out
 
 
-def transport_leg(torch, config, steps=20, warmup=3, evolve_steps=40):
+def transport_leg(torch, config, steps=20, warmup=3, evolve_yr=10.0):
     """The transport step of the dynamics solver on `config`'s grid and
     species (Sec. 3): `steps` CFL steps from the disc's initial state, each
     step's two kernels timed with HIP events on the current stream; HBM
     roofline of the step with 160 algorithmic bytes per (cell, species) (the
     state at t^n read twice, the half-step state written once and read once,
     the new state written: 5 x 32 bytes); then the scheduler (coag_evolve,
-    FP64 coagulation) over `evolve_steps` CFL steps of the same state."""
+    FP64 coagulation) over `evolve_yr` years from the disc's initial state."""
     from paper_2402_18471_amd import disc
     from paper_2402_18471_amd.coag import TransportContext, coag_create, coag_mass_grid
     cfg = disc.CONFIGS[config]
@@ -651,7 +651,7 @@ def transport_leg(torch, config, steps=20, warmup=3, evolve_steps=40):
     rho, v = t(d["rho"]), t(d["v"])
     h = torch.zeros(C, dtype=torch.float64, device=dev)
     vf = t(d["v_frag"])
-    t_end = evolve_steps * tc.dt(cells, v)
+    t_end = evolve_yr * 3.15576e7
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     st = tc.evolve(ctx, cells, vg, vf, rho, v, h, t_end)

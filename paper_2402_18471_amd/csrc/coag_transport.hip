@@ -297,21 +297,25 @@ __global__ __launch_bounds__(kTBlock) void k_tr_full(TGeo g, Gas gas, double *rh
 // positive doubles order like their bit patterns: the minimum via atomicMin on them
 __global__ void k_tr_fill(unsigned long long *x, unsigned long long val) { *x = val; }
 
+// each block strides over the (cell, species) pairs and adds one atomic: a
+// bounded grid keeps the atomics on the one word few
+constexpr int kCflBlocks = 1024;
+
 __global__ __launch_bounds__(kTBlock) void k_tr_cfl(TGeo g, Gas gas, const double *v,
                                                      double c_adv, double c_diff,
                                                      unsigned long long *out) {
     __shared__ double red[kTBlock / 64];
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long C = (long)g.nr * g.nz;
     double m = INFINITY;
-    if (t < C * g.N) {
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < C * g.N;
+         t += (long)gridDim.x * blockDim.x) {
         const long c = t / g.N;
         const int i = (int)(c / g.nz), j = (int)(c - (long)i * g.nz);
         const double dR = g.dR[i], dZ = g.Rc[i] * (g.te[j + 1] - g.te[j]);
         const double a = fmin(fabs(dR / v[3 * t]), fabs(dZ / v[3 * t + 2]));
         const double k = gas.alpha[c] * gas.c_s[c] * gas.H[c] / g.Sc;
         const double d = fmin(dR * dR / k, dZ * dZ / k);
-        m = fmin(c_adv * a, c_diff * d);
+        m = fmin(m, fmin(c_adv * a, c_diff * d));
     }
     for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -536,7 +540,8 @@ int coag_transport_dt(coag_tctx *t, const coag_cells *cells, const double *v, do
     hipStream_t st = (hipStream_t)stream;
     const long n = (long)t->nr * t->nz * t->N;
     hipLaunchKernelGGL(k_tr_fill, dim3(1), dim3(1), 0, st, t->red, 0x7FF0000000000000ull);
-    hipLaunchKernelGGL(k_tr_cfl, dim3((unsigned)((n + kTBlock - 1) / kTBlock)), dim3(kTBlock), 0, st,
+    const long nb = std::min<long>((n + kTBlock - 1) / kTBlock, kCflBlocks);
+    hipLaunchKernelGGL(k_tr_cfl, dim3((unsigned)std::max<long>(nb, 1)), dim3(kTBlock), 0, st,
                        t->geo, gas_of(cells, nullptr), v, t->c_adv, t->c_diff, t->red);
     THIP(t, hipGetLastError());
     unsigned long long bits = 0;
