@@ -230,16 +230,27 @@ __device__ inline double stop_time(const TGeo &g, const Gas &gas, long c, int s)
     return g.rho_m * g.s[s] / (gas.rho_g[c] * v_th);
 }
 
+// Each wave takes the species of one cell (lane = species within a run of
+// 64): the cell's index, and so every gas and geometry operand, is uniform
+// over the wave and read through the scalar cache; only the states of the
+// stencil are vector loads.  The waves of a cell are ceil(N / 64) in a row.
+__device__ inline bool wave_cell(const TGeo &g, long &c, int &s) {
+    const int wpc = (g.N + 63) >> 6;                 // waves per cell
+    const long w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kTBlock / 64) + (threadIdx.x >> 6)));
+    c = w / wpc;
+    s = (int)(w - c * wpc) * 64 + (int)(threadIdx.x & 63);
+    return c < (long)g.nr * g.nz && s < g.N;
+}
+
 // Stages (i)-(iv): first-order fluxes at t^n, half update, half source,
 // primitives, half drag -> the half-step state (rh, vh)
 __global__ __launch_bounds__(kTBlock) void k_tr_half(TGeo g, Gas gas, const double *rho,
                                                       const double *v, double *rh, double *vh,
                                                       double dt) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long C = (long)g.nr * g.nz;
-    if (t >= C * g.N) return;
-    const long c = t / g.N;
-    const int s = (int)(t - c * g.N);
+    long c;
+    int s;
+    if (!wave_cell(g, c, s)) return;
+    const long t = c * g.N + s;
     const int i = (int)(c / g.nz), j = (int)(c - (long)i * g.nz);
     double FA[4];
     flux_area<1>(g, gas, rho, v, i, j, s, FA);
@@ -267,11 +278,10 @@ __global__ __launch_bounds__(kTBlock) void k_tr_half(TGeo g, Gas gas, const doub
 __global__ __launch_bounds__(kTBlock) void k_tr_full(TGeo g, Gas gas, double *rho, double *v,
                                                       const double *rh, const double *vh,
                                                       double dt) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long C = (long)g.nr * g.nz;
-    if (t >= C * g.N) return;
-    const long c = t / g.N;
-    const int s = (int)(t - c * g.N);
+    long c;
+    int s;
+    if (!wave_cell(g, c, s)) return;
+    const long t = c * g.N + s;
     const int i = (int)(c / g.nz), j = (int)(c - (long)i * g.nz);
     double FA[4];
     flux_area<2>(g, gas, rh, vh, i, j, s, FA);
@@ -561,8 +571,8 @@ int coag_transport_step(coag_tctx *t, const coag_cells *cells, const double *v_g
     if (!(dt > 0.0) || !std::isfinite(dt))
         return tfail(t, COAG_EINVAL, "coag_transport_step: dt = %g", dt);
     hipStream_t st = (hipStream_t)stream;
-    const long n = (long)t->nr * t->nz * t->N;
-    const dim3 grid((unsigned)((n + kTBlock - 1) / kTBlock));
+    const long waves = (long)t->nr * t->nz * ((t->N + 63) / 64);
+    const dim3 grid((unsigned)((waves + kTBlock / 64 - 1) / (kTBlock / 64)));
     const Gas gas = gas_of(cells, v_gas);
     hipLaunchKernelGGL(k_tr_half, grid, dim3(kTBlock), 0, st, t->geo, gas, rho, v, t->rh, t->vh, dt);
     hipLaunchKernelGGL(k_tr_full, grid, dim3(kTBlock), 0, st, t->geo, gas, rho, v, t->rh, t->vh, dt);
