@@ -39,7 +39,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
-KERNEL_SRC = os.path.join(ROOT, "paper_2402_18471_amd", "csrc", "coag_batch.hip")
+# what the batched step's code object is built from: its sources, the headers
+# it includes and the build flags
+KERNEL_FILES = [os.path.join("csrc", f) for f in ("coag_batch.hip", "coag_batch.h",
+                                                    "coag_batch_common.h", "coag_launch.h",
+                                                    "coag_device.h")] + ["build.py"]
 COUNTERS = os.path.join(ROOT, "profiles", "kernel_counters.json")
 
 
@@ -268,9 +272,7 @@ def summarize_counters(out_json, bench_log, trace_csv, *pmc_csvs):
     w_fac = (1 << 30) / (w_cal["WRITE_SIZE"] * 1024.0)
     b = json.loads([ln for ln in open(bench_log) if ln.startswith("{")][-1])
     disc_grid = -(-b["config"]["cells"] // 16) * 512          # threads of a step launch
-    src = os.path.join(ROOT, "paper_2402_18471_amd", "csrc")
-    shas = {f: hashlib.sha256(open(os.path.join(src, f), "rb").read()).hexdigest()
-            for f in ("coag_batch.hip", "coag_adjoint.hip", "coag_kernels.hip", "coag_rate.h")}
+    shas = kernel_shas()
     out = {"kernel_sources_sha256": shas,
            "workload": f"{b['config']['workload']} (bench.py --steps 1 --warmup 1); adjoint "
                        "kernels from its adjoint legs", "calibration": {
@@ -320,21 +322,28 @@ def summarize_counters(out_json, bench_log, trace_csv, *pmc_csvs):
     print(json.dumps(out))
 
 
+def kernel_shas():
+    """SHA-256 of every file the batched step's code object is built from."""
+    import hashlib
+    pkg = os.path.join(ROOT, "paper_2402_18471_amd")
+    return {f: hashlib.sha256(open(os.path.join(pkg, f), "rb").read()).hexdigest()
+            for f in KERNEL_FILES}
+
+
 def profiled_traffic(rhs_per_launch, kind):
     """HBM bytes per launch of the batched step kernel (FP64 or split form) on
     the bench disc from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE of the timed launch, calibrated on a device copy, scaled per
-    cell right-hand side), or None when there is none or the kernel source
-    has changed since the counters were taken."""
-    import hashlib
+    cell right-hand side), or None when there is none or any file the kernel
+    is built from (sources, headers, build flags) has changed since the
+    counters were taken."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
-        with open(KERNEL_SRC, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        shas = kernel_shas()
     except OSError:
         return None
-    if c.get("kernel_sources_sha256", {}).get("coag_batch.hip") != sha:
+    if c.get("kernel_sources_sha256") != shas:
         return None
     want = "k_step_batch<0, double, true>" if kind == "fp64" else "k_step_batch<1, float, true>"
     grp = [g for g in c["groups"] if g["kernel"] == want and "fetch_bytes" in g]
