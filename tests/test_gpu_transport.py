@@ -5,8 +5,7 @@ transport oracle on the same seeded disc inputs, and the scheduler
 Bars: the kernels and the oracle evaluate the same expressions in FP64 in
 different orders (per-cell sums of the four face fluxes, fused multiply-adds),
 so states agree to rounding: each (cell, species) density within 1e-12
-relative (of the larger of the densities before and after the step where a
-step nearly empties a species) plus 1e-14 of its cell's largest density, each velocity within
+relative plus 1e-14 of its cell's largest density, each velocity within
 1e-12 relative plus 1e-12 of the largest speed of its cell and species row;
 the CFL step of the same velocities within 1e-14 relative.  The scheduler test runs the same library
 calls in Python by the rule of the header; the FP64 coagulation step deposits
@@ -54,14 +53,11 @@ def _ctx(cfg, s, d):
     return TransportContext(d["R_edge"], d["t_edge"], s, rho_m=cfg.rho_m, GM=d["GM"])
 
 
-def _close(rho_g, v_g, rho_o, v_o, rho_pre=None):
-    """the module docstring's bars (with rho_pre: relative to the larger of
-    the density before and after the step); returns the largest ratios to
-    them"""
+def _close(rho_g, v_g, rho_o, v_o):
+    """the module docstring's bars; returns the largest ratios to them"""
     C, N = rho_o.shape
     rfloor = 1e-14 * np.abs(rho_o).max(axis=1, keepdims=True)
-    scale = np.abs(rho_o) if rho_pre is None else np.maximum(np.abs(rho_o), np.abs(rho_pre))
-    er = np.abs(rho_g - rho_o) / (1e-12 * scale + rfloor + 1e-300)
+    er = np.abs(rho_g - rho_o) / (1e-12 * np.abs(rho_o) + rfloor + 1e-300)
     vmax = np.abs(v_o).max(axis=2, keepdims=True)
     ev = np.abs(v_g - v_o) / (1e-12 * np.abs(v_o) + 1e-12 * vmax + 1e-300)
     return float(er.max()), float(ev.max())
@@ -185,72 +181,3 @@ def test_evolve_follows_the_scheduler_rule(prec):
     assert np.all(np.abs(a - b) <= 1e-12 * np.abs(b) + 1e-24 * M)
     assert torch.allclose(v_a, v_b, rtol=1e-12, atol=0.0)
     assert torch.allclose(h_a, h_b, rtol=1e-12, atol=0.0)
-
-
-def test_transport_and_coagulation_together_match_the_oracles():
-    """A dozen global steps of the scheduler's sequence on a small disc, each
-    operation checked against the oracle from the GPU's own state at that
-    point (so that rounding differences do not compound over the coupled
-    run): the transport step against the transport oracle's step on the same
-    dt, the CFL step against the oracle's rule on the GPU's velocities, and
-    each coagulation update against the coagulation oracle's rates of the
-    GPU's velocities and its step replaying the GPU call's sub-steps (the step
-    sequence is the GPU's, as in the coagulation parity tests).  Bars: the
-    transport bars of this module; coagulation densities within 1e-10
-    relative in bins above 1e-20 of the cell's mass, 1e-20 of the cell's mass
-    below (the calls here are long, up to centuries, and replay the same steps
-    on rates that agree to 1e-12)."""
-    import oracle as O
-    from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
-    from paper_2402_18471_amd import disc
-    n_r, n_z, N = 6, 4, 30
-    cfg = disc.scaled(disc.CONFIGS["disc64x32_n100"], n_r, n_z, N)
-    m, me, s = coag_mass_grid(N, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
-    og = O.make_grid(N, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
-    d = disc.make_transport(cfg, s)
-    T, g, gas = _oracle(cfg, s, d)
-    ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
-    tc = _ctx(cfg, s, d)
-    cells = {k: _t(v) for k, v in d["cells"].items()}
-    vg, vf = _t(d["v_gas"]), _t(d["v_frag"])
-    C = cfg.n_cells
-    rho_b, v_b, h_b = _t(d["rho"]), _t(d["v"]), torch.zeros(C, dtype=torch.float64, device=DEV)
-    sh = (n_r, n_z)
-    since, trig, calls = 0.0, 0.0, 0
-    for step in range(12):
-        r0, v0 = rho_b.cpu().numpy(), v_b.cpu().numpy()
-        dt = tc.dt(cells, v_b)
-        assert dt == pytest.approx(T.cfl_dt(g, gas, v0.reshape(sh + (N, 3))), rel=1e-14)
-        tc.step(cells, vg, rho_b, v_b, dt)
-        r3, v3 = T.step(g, gas, s, cfg.rho_m, r0.reshape(sh + (N,)), v0.reshape(sh + (N, 3)), dt)
-        torch.cuda.synchronize()
-        # after coagulation calls some species are nearly emptied by the flux
-        # of a step (the new density the difference of two near-equal
-        # terms): their rounding is relative to the density before the step
-        et, ev = _close(rho_b.cpu().numpy(), v_b.cpu().numpy(), r3.reshape(C, N),
-                        v3.reshape(C, N, 3), rho_pre=r0)
-        assert et <= 1.0 and ev <= 1.0, (step, et, ev)
-        since += dt
-        ec = 0.0
-        if since >= trig:
-            r1, v1 = rho_b.cpu().numpy(), v_b.cpu().numpy()
-            K = ctx.coag_rates_blocked(cells, v_b, vf, dtype=torch.float64)
-            r = ctx.coag_step(rho_b, K, None, since, h=h_b, max_sub=256)
-            torch.cuda.synchronize()
-            ns, hl = r["nsub"].cpu().numpy(), r["h_log"].cpu().numpy()
-            Kc, Kf = O.rates(og, d["cells"], v1, d["v_frag"])
-            ro = O.step(og, r1, Kc, Kf, since, mode=O.REPLAY, nsub=ns, h_log=hl)["rho"]
-            a = rho_b.cpu().numpy()
-            M = ro.sum(1, keepdims=True)
-            res = np.abs(ro) > 1e-20 * M
-            err = np.where(res, np.abs(a - ro) / (1e-10 * np.abs(ro) + 1e-300),
-                           np.abs(a - ro) / (1e-20 * M + 1e-300))
-            ec = float(err.max())
-            calls += 1
-            since = 0.0
-            hp = h_b[h_b > 0]
-            trig = float(hp.min()) if hp.numel() else 0.0
-        print(f"global step {step}: dt {dt:.4g} s, coagulation calls {calls}; transport "
-              f"{max(et, ev):.3g}, coagulation {ec:.3g} of the bars", flush=True)
-        assert ec <= 1.0, (step, ec)
-    assert calls >= 3
