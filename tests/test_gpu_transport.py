@@ -7,7 +7,8 @@ different orders (per-cell sums of the four face fluxes, fused multiply-adds),
 so states agree to rounding: each (cell, species) density within 1e-12
 relative plus 1e-14 of its cell's largest density, each velocity within
 1e-12 relative plus 1e-12 of the largest speed of its cell and species row;
-the CFL step of the same velocities within 1e-14 relative.  The scheduler test runs the same library
+the CFL step within 1e-14 relative from the same inputs (1e-9 after steps,
+each side from its own velocities).  The scheduler test runs the same library
 calls in Python by the rule of the header; the FP64 coagulation step deposits
 with LDS atomics whose order may differ between launches, so densities agree
 to 1e-12 relative (floor 1e-24 of the cell's mass) and the counts exactly.
@@ -74,12 +75,13 @@ def test_transport_steps_match_the_oracle(shape):
     ro = d["rho"].reshape(n_r, n_z, N).copy()
     vo = d["v"].reshape(n_r, n_z, N, 3).copy()
     for k in range(2 if N > 100 else 3):
-        # the CFL rule on the same velocities (the GPU's): the same minimum
+        # the CFL rule: the same minimum from the same inputs at the start;
+        # later each side from its own velocities (equal to the bars above,
+        # the limiting component possibly far below the row's largest)
         dt_g = tc.dt(cells, v)
-        dt_c = T.cfl_dt(g, gas, v.cpu().numpy().reshape(n_r, n_z, N, 3))
-        assert dt_g == pytest.approx(dt_c, rel=1e-14), (k, dt_g, dt_c)
-        # both sides step by the oracle's own step size
         dt_o = T.cfl_dt(g, gas, vo)
+        assert dt_g == pytest.approx(dt_o, rel=1e-14 if k == 0 else 1e-9), (k, dt_g, dt_o)
+        # both sides step by the oracle's step size
         tc.step(cells, vg, rho, v, dt_o)
         ro, vo = T.step(g, gas, s, cfg.rho_m, ro, vo, dt_o)
         torch.cuda.synchronize()
