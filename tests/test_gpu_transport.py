@@ -64,7 +64,8 @@ def _close(rho_g, v_g, rho_o, v_o):
     return float(er.max()), float(ev.max())
 
 
-@pytest.mark.parametrize("shape", [(24, 12, 12), (5, 3, 7), (1, 1, 4), (128, 64, 150)])
+@pytest.mark.parametrize("shape", [(24, 12, 12), (5, 3, 7), (1, 1, 4), (128, 64, 150),
+                                   (2, 3, 1023)])
 def test_transport_steps_match_the_oracle(shape):
     n_r, n_z, N = shape
     cfg, s, d = _inputs(n_r, n_z, N)
@@ -183,3 +184,31 @@ def test_evolve_follows_the_scheduler_rule(prec):
     assert np.all(np.abs(a - b) <= 1e-12 * np.abs(b) + 1e-24 * M)
     assert torch.allclose(v_a, v_b, rtol=1e-12, atol=0.0)
     assert torch.allclose(h_a, h_b, rtol=1e-12, atol=0.0)
+
+
+def test_a_disc_at_rest_has_no_cfl_limit():
+    """No velocity, no turbulence and no gravity: no component limits the
+    step, the CFL step is +inf, and the scheduler covers t_end in one
+    transport step (which moves nothing) with one coagulation update over all
+    of it."""
+    from paper_2402_18471_amd.coag import coag_create, coag_mass_grid
+    from paper_2402_18471_amd import disc
+    n_r, n_z, N = 4, 3, 20
+    cfg = disc.scaled(disc.CONFIGS["disc64x32_n100"], n_r, n_z, N)
+    m, me, s = coag_mass_grid(N, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
+    d = disc.make_transport(cfg, s)
+    d["cells"]["alpha"][:] = 0.0
+    d["GM"] = 0.0
+    tc = _ctx(cfg, s, d)
+    cells = {k: _t(v) for k, v in d["cells"].items()}
+    v = torch.zeros((cfg.n_cells, N, 3), dtype=torch.float64, device=DEV)
+    assert tc.dt(cells, v) == float("inf")
+    ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
+    rho = _t(d["rho"])
+    h = torch.zeros(cfg.n_cells, dtype=torch.float64, device=DEV)
+    vg = torch.zeros((cfg.n_cells, 3), dtype=torch.float64, device=DEV)
+    st = tc.evolve(ctx, cells, vg, _t(d["v_frag"]), rho, v, h, 100.0 * 3.15576e7, prec=0)
+    torch.cuda.synchronize()
+    assert st["transport_steps"] == 1 and st["coag_calls"] == 1 and st["cells_failed"] == 0
+    assert st["t_reached"] == 100.0 * 3.15576e7
+    assert torch.count_nonzero(v) == 0 and bool(torch.all(h > 0))
