@@ -58,8 +58,9 @@ typedef struct {
 
 /* Create a transport context on the current device for N species of grain
    radii s (HOST [N], cm) and material density rho_m: the grid's geometry
-   tables and the half-step workspace (4 C N doubles).  Errors: COAG_EINVAL,
-   COAG_ENOMEM, COAG_EHIP. */
+   tables, the half-step workspace (4 C N doubles) and the gas tables each
+   step refreshes (about 4 C doubles).  Errors: COAG_EINVAL, COAG_ENOMEM,
+   COAG_EHIP. */
 int coag_transport_create(const coag_tgrid *grid, int32_t N, const double *s, double rho_m,
                           coag_tctx **out);
 

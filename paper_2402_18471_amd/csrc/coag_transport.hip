@@ -8,11 +8,13 @@
 // Each thread evaluates the fluxes through its own cell's four faces (a face
 // shared by two cells is evaluated by both, from the same operands in the
 // same order, hence to the same bits: the update stays conservative without
-// a separate face pass or atomics).  The step is HBM-bound: per (cell,
-// species) the two kernels read the state at t^n and the half-step state
-// of the cell and its neighbours (mostly from L2) and write the half-step
-// state and the new state.
+// a separate face pass or atomics).  The step is bound by FP64 vector issue:
+// per (cell, species) the two kernels evaluate six face fluxes with their
+// square roots and, in the second stage, twelve limited slopes; whatever
+// depends on the cell alone (geometry, gas, diffusion coefficients of the
+// faces, reciprocals) comes from tables, read through the scalar cache.
 #include <hip/hip_runtime.h>
+#include <float.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -26,6 +28,7 @@
 #include "../../include/coag.h"
 #include "../../include/coag_transport.h"
 #include "coag_launch.h"
+#include "coag_rate.h"
 
 namespace coag {
 
@@ -51,7 +54,25 @@ struct TGeo {
     const double *AR;        // [(nr + 1) * nz] cylinder-face areas
     const double *At;        // [nr * (nz + 1)] cone-face areas
     const double *s;         // [N] grain radii
+    const double *iRc;       // [nr] 1 / R_c
+    const double *irx;       // [nr + 3] 1 / (Rx[k+1] - Rx[k]), k = -2 .. nr
+    const double *itx;       // [nz + 3] 1 / (tx[k+1] - tx[k]), k = -2 .. nz
+    const double *nRt;       // [nz + 1] unit normal of cone face j: (nRt, nZt) = (-t, 1) / sqrt(1 + t^2)
+    const double *nZt;       // [nz + 1]
+    const double *iV;        // [nr * nz] 1 / V
+    const double *om2;       // [nr * nz] GM / r^3 at the cell centre
     double rho_m, GM, Sc;
+};
+
+// per-step tables of the gas (k_tr_prep): 1 / rho_g, the stopping time per
+// unit grain radius, and each face's diffusion coefficient over the distance
+// between the cells it joins (0 at the grid's outer faces and the midplane)
+struct GasT {
+    const double *irg;       // [C]
+    const double *tsf;       // [C] t_stop / s
+    const double *KR;        // [(nr + 1) * nz] cylinder faces
+    const double *Kt;        // [nr * (nz + 1)] cone faces
+    const double *v_g;       // [C][3]
 };
 
 struct Gas {
@@ -79,16 +100,16 @@ __device__ inline Prim fetch(const TGeo &g, const double *rho, const double *v, 
     return p;
 }
 
-// van Leer's harmonic mean of two one-sided gradients (0 where they differ in sign)
+// van Leer's harmonic mean of two one-sided gradients (0 where they differ in
+// sign).  Where a b > 0 in FP64, |a + b| >= sqrt(a b) is normal, so the refined
+// hardware reciprocal of div_nr applies.
 __device__ inline double vanleer(double a, double b) {
-    return a * b > 0.0 ? 2.0 * a * b / (a + b) : 0.0;
+    return a * b > 0.0 ? div_nr(2.0 * a * b, a + b) : 0.0;
 }
 
-// limited slope of each primitive of cell m from its neighbours l and r at
-// coordinates xl < xm < xr
-__device__ inline Prim slope(const Prim &l, const Prim &m, const Prim &r, double xl, double xm,
-                             double xr) {
-    const double il = 1.0 / (xm - xl), ir = 1.0 / (xr - xm);
+// limited slope of each primitive of cell m from its neighbours l and r;
+// il, ir the inverse distances m - l and r - m
+__device__ inline Prim slope(const Prim &l, const Prim &m, const Prim &r, double il, double ir) {
     Prim g;
     g.r = vanleer((m.r - l.r) * il, (r.r - m.r) * ir);
     g.vR = vanleer((m.vR - l.vR) * il, (r.vR - m.vR) * ir);
@@ -135,22 +156,29 @@ __device__ inline void face_flux(const Prim &L, const Prim &R, double nR, double
 }
 
 // explicit sources (curvature, gravity) of eq. `sources` at the cell centre
-__device__ inline void sources(const Prim &p, double R, double Z, double GM, double S[4]) {
-    const double r2 = R * R + Z * Z;
-    const double om2 = GM / (r2 * sqrt(r2));
+// (R, Z), iR = 1 / R, om2 = GM / r^3
+__device__ inline void sources(const Prim &p, double R, double iR, double Z, double om2,
+                               double S[4]) {
     S[0] = 0.0;
-    S[1] = p.r * p.vp * p.vp / R - p.r * (om2 * R);
+    S[1] = p.r * p.vp * p.vp * iR - p.r * (om2 * R);
     S[2] = 0.0;
     S[3] = -p.r * (om2 * Z);
 }
 
-// primitives of Q (radius R of the angular momentum); empty cells at rest
-__device__ inline Prim primitive(const double Q[4], double R) {
+// primitives of Q (iR = 1 / the radius of the angular momentum); empty cells at rest
+__device__ inline Prim primitive(const double Q[4], double iR) {
     Prim p;
     p.r = Q[0];
-    if (Q[0] > 0.0) {
+    if (Q[0] >= DBL_MIN) {
+        const double iq = 1.0 / Q[0];
+        p.vR = Q[1] * iq;
+        p.vp = Q[2] * iq * iR;
+        p.vZ = Q[3] * iq;
+    } else if (Q[0] > 0.0) {
+        // a subnormal density (the coagulation update leaves such tails in
+        // the upper bins): 1 / Q[0] would overflow, the quotients do not
         p.vR = Q[1] / Q[0];
-        p.vp = Q[2] / (Q[0] * R);
+        p.vp = Q[2] / Q[0] * iR;
         p.vZ = Q[3] / Q[0];
     } else {
         p.vR = p.vp = p.vZ = 0.0;
@@ -162,7 +190,7 @@ __device__ inline Prim primitive(const double Q[4], double R) {
 // from states P (order 1: the cells' own values; order 2: piecewise linear)
 // and the diffusive flux of eps = rho / rho_g between the cells.
 template <int ORDER>
-__device__ void flux_area(const TGeo &g, const Gas &gas, const double *rho, const double *v,
+__device__ void flux_area(const TGeo &g, const GasT &gas, const double *rho, const double *v,
                           int i, int j, int s, double FA[4]) {
     const int nr = g.nr, nz = g.nz;
     const long c = (long)i * nz + j;
@@ -175,59 +203,61 @@ __device__ void flux_area(const TGeo &g, const Gas &gas, const double *rho, cons
     if (ORDER == 2) {
         const Prim Pww = fetch(g, rho, v, i - 2, j, s), Pee = fetch(g, rho, v, i + 2, j, s);
         const Prim Pss = fetch(g, rho, v, i, j - 2, s), Pnn = fetch(g, rho, v, i, j + 2, s);
-        const double *Rx = g.Rx + 2, *tx = g.tx + 2;  // index -2 .. n + 1
-        const Prim gw = slope(Pww, Pw, P0, Rx[i - 2], Rx[i - 1], Rx[i]);
-        const Prim g0 = slope(Pw, P0, Pe, Rx[i - 1], Rx[i], Rx[i + 1]);
-        const Prim ge = slope(P0, Pe, Pee, Rx[i], Rx[i + 1], Rx[i + 2]);
+        const double *Rx = g.Rx + 2, *tx = g.tx + 2;     // index -2 .. n + 1
+        const double *irx = g.irx + 2, *itx = g.itx + 2; // index -2 .. n
+        const Prim gw = slope(Pww, Pw, P0, irx[i - 2], irx[i - 1]);
+        const Prim g0 = slope(Pw, P0, Pe, irx[i - 1], irx[i]);
+        const Prim ge = slope(P0, Pe, Pee, irx[i], irx[i + 1]);
         Lw = extrap(Pw, gw, g.Re[i] - Rx[i - 1]);
         Rw = extrap(P0, g0, g.Re[i] - Rx[i]);
         Le = extrap(P0, g0, g.Re[i + 1] - Rx[i]);
         Re = extrap(Pe, ge, g.Re[i + 1] - Rx[i + 1]);
-        const Prim gs = slope(Pss, Ps, P0, tx[j - 2], tx[j - 1], tx[j]);
-        const Prim h0 = slope(Ps, P0, Pn, tx[j - 1], tx[j], tx[j + 1]);
-        const Prim gn = slope(P0, Pn, Pnn, tx[j], tx[j + 1], tx[j + 2]);
+        const Prim gs = slope(Pss, Ps, P0, itx[j - 2], itx[j - 1]);
+        const Prim h0 = slope(Ps, P0, Pn, itx[j - 1], itx[j]);
+        const Prim gn = slope(P0, Pn, Pnn, itx[j], itx[j + 1]);
         Ls = extrap(Ps, gs, g.te[j] - tx[j - 1]);
         Rs = extrap(P0, h0, g.te[j] - tx[j]);
         Ln = extrap(P0, h0, g.te[j + 1] - tx[j]);
         Rn = extrap(Pn, gn, g.te[j + 1] - tx[j + 1]);
     }
-    // diffusion: -(rho_g nu / Sc)_face (eps_r - eps_l) / d through interior faces
-    auto D = [&](long k) { return gas.rho_g[k] * (gas.alpha[k] * gas.c_s[k] * gas.H[k]) / g.Sc; };
-    auto eps = [&](const Prim &p, long k) { return p.r / gas.rho_g[k]; };
-    const double D0 = D(c), e0 = eps(P0, c);
-    double Fw = 0.0, Fe = 0.0, Fs = 0.0, Fn = 0.0;
-    if (i > 0) {
-        const long k = c - nz;
-        Fw = -(0.5 * (D(k) + D0)) * (e0 - eps(Pw, k)) / (g.Rc[i] - g.Rc[i - 1]);
-    }
-    if (i < nr - 1) {
-        const long k = c + nz;
-        Fe = -(0.5 * (D0 + D(k))) * (eps(Pe, k) - e0) / (g.Rc[i + 1] - g.Rc[i]);
-    }
-    const double tS = g.te[j], tN = g.te[j + 1];
-    const double cS = 1.0 / sqrt(1.0 + tS * tS), cN = 1.0 / sqrt(1.0 + tN * tN);
-    if (j > 0) {
-        const long k = c - 1;
-        Fs = -(0.5 * (D(k) + D0)) * (e0 - eps(Ps, k)) / (cS * g.Rc[i] * (g.tc[j] - g.tc[j - 1]));
-    }
-    if (j < nz - 1) {
-        const long k = c + 1;
-        Fn = -(0.5 * (D0 + D(k))) * (eps(Pn, k) - e0) / (cN * g.Rc[i] * (g.tc[j + 1] - g.tc[j]));
-    }
+    // diffusion: -K (eps_r - eps_l), eps = rho / rho_g, K the face's
+    // coefficient over the cells' distance (0 where the grid ends: the ghost
+    // cells' eps, taken from the cells they copy, then carry no flux)
+    const long kw = i > 0 ? c - nz : c, ke = i < nr - 1 ? c + nz : c;
+    const long ks = j > 0 ? c - 1 : c, kn = j < nz - 1 ? c + 1 : c;
+    const double e0 = P0.r * gas.irg[c];
+    const double Fw = -gas.KR[c] * (e0 - Pw.r * gas.irg[kw]);
+    const double Fe = -gas.KR[c + nz] * (Pe.r * gas.irg[ke] - e0);
+    const long ft = (long)i * (nz + 1) + j;
+    const double Fs = -gas.Kt[ft] * (e0 - Ps.r * gas.irg[ks]);
+    const double Fn = -gas.Kt[ft + 1] * (Pn.r * gas.irg[kn] - e0);
     double fw[4], fe[4], fs[4], fn[4];
     face_flux(Lw, Rw, 1.0, 0.0, g.Re[i], Fw, fw);
     face_flux(Le, Re, 1.0, 0.0, g.Re[i + 1], Fe, fe);
-    face_flux(Ls, Rs, -tS * cS, cS, g.Rcone[i], Fs, fs);
-    face_flux(Ln, Rn, -tN * cN, cN, g.Rcone[i], Fn, fn);
-    const double aw = g.AR[(long)i * nz + j], ae = g.AR[(long)(i + 1) * nz + j];
-    const double as = g.At[(long)i * (nz + 1) + j], an = g.At[(long)i * (nz + 1) + j + 1];
+    face_flux(Ls, Rs, g.nRt[j], g.nZt[j], g.Rcone[i], Fs, fs);
+    face_flux(Ln, Rn, g.nRt[j + 1], g.nZt[j + 1], g.Rcone[i], Fn, fn);
+    const double aw = g.AR[c], ae = g.AR[c + nz];
+    const double as = g.At[ft], an = g.At[ft + 1];
 #pragma unroll
     for (int k = 0; k < 4; ++k) FA[k] = ((0.0 - fw[k] * aw) + fe[k] * ae) - fs[k] * as + fn[k] * an;
 }
 
-__device__ inline double stop_time(const TGeo &g, const Gas &gas, long c, int s) {
-    const double v_th = sqrt(8.0 / M_PI) * gas.c_s[c];
-    return g.rho_m * g.s[s] / (gas.rho_g[c] * v_th);
+// the tables of GasT from the gas arrays (one thread per cell)
+__global__ __launch_bounds__(kTBlock) void k_tr_prep(TGeo g, Gas gas, double *irg, double *tsf,
+                                                      double *KR, double *Kt) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nr = g.nr, nz = g.nz;
+    if (c >= (long)nr * nz) return;
+    const int i = (int)(c / nz), j = (int)(c - (long)i * nz);
+    auto D = [&](long k) { return gas.rho_g[k] * (gas.alpha[k] * gas.c_s[k] * gas.H[k]) / g.Sc; };
+    const double D0 = D(c);
+    irg[c] = 1.0 / gas.rho_g[c];
+    tsf[c] = g.rho_m / (gas.rho_g[c] * (sqrt(8.0 / M_PI) * gas.c_s[c]));
+    KR[c] = i > 0 ? 0.5 * (D(c - nz) + D0) / (g.Rc[i] - g.Rc[i - 1]) : 0.0;
+    if (i == nr - 1) KR[c + nz] = 0.0;
+    const long ft = (long)i * (nz + 1) + j;
+    Kt[ft] = j > 0 ? 0.5 * (D(c - 1) + D0) / (g.nZt[j] * g.Rc[i] * (g.tc[j] - g.tc[j - 1])) : 0.0;
+    if (j == nz - 1) Kt[ft + 1] = 0.0;
 }
 
 // Each wave takes the species of one cell (lane = species within a run of
@@ -244,7 +274,7 @@ __device__ inline bool wave_cell(const TGeo &g, long &c, int &s) {
 
 // Stages (i)-(iv): first-order fluxes at t^n, half update, half source,
 // primitives, half drag -> the half-step state (rh, vh)
-__global__ __launch_bounds__(kTBlock) void k_tr_half(TGeo g, Gas gas, const double *rho,
+__global__ __launch_bounds__(kTBlock) void k_tr_half(TGeo g, GasT gas, const double *rho,
                                                       const double *v, double *rh, double *vh,
                                                       double dt) {
     long c;
@@ -254,17 +284,17 @@ __global__ __launch_bounds__(kTBlock) void k_tr_half(TGeo g, Gas gas, const doub
     const int i = (int)(c / g.nz), j = (int)(c - (long)i * g.nz);
     double FA[4];
     flux_area<1>(g, gas, rho, v, i, j, s, FA);
-    const double R = g.Rc[i], Z = g.tc[j] * g.Rc[i];
+    const double R = g.Rc[i], iR = g.iRc[i], Z = g.tc[j] * g.Rc[i];
     const Prim P = {rho[t], v[3 * t], v[3 * t + 1], v[3 * t + 2]};
     const double Q[4] = {P.r, P.r * P.vR, P.r * P.vp * R, P.r * P.vZ};
     double S[4];
-    sources(P, R, Z, g.GM, S);
-    const double f = 0.5 * dt / g.V[c];
+    sources(P, R, iR, Z, g.om2[c], S);
+    const double f = 0.5 * dt * g.iV[c];
     double Qs[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) Qs[k] = (Q[k] - f * FA[k]) + 0.5 * dt * S[k];
-    Prim H = primitive(Qs, R);
-    const double hd = 0.5 * dt, w = hd / (hd + stop_time(g, gas, c, s));
+    Prim H = primitive(Qs, iR);
+    const double hd = 0.5 * dt, w = hd / (hd + gas.tsf[c] * g.s[s]);
     const double *vg = gas.v_g + 3 * c;
     rh[t] = H.r;
     vh[3 * t] = H.vR - w * (H.vR - vg[0]);
@@ -275,7 +305,7 @@ __global__ __launch_bounds__(kTBlock) void k_tr_half(TGeo g, Gas gas, const doub
 // Stages (v)-(viii): second-order fluxes at t^{n+1/2}, full update from t^n,
 // full source at t^{n+1/2}, primitives, full drag, in place on (rho, v)
 // (a thread reads only its own cell's t^n state)
-__global__ __launch_bounds__(kTBlock) void k_tr_full(TGeo g, Gas gas, double *rho, double *v,
+__global__ __launch_bounds__(kTBlock) void k_tr_full(TGeo g, GasT gas, double *rho, double *v,
                                                       const double *rh, const double *vh,
                                                       double dt) {
     long c;
@@ -285,18 +315,18 @@ __global__ __launch_bounds__(kTBlock) void k_tr_full(TGeo g, Gas gas, double *rh
     const int i = (int)(c / g.nz), j = (int)(c - (long)i * g.nz);
     double FA[4];
     flux_area<2>(g, gas, rh, vh, i, j, s, FA);
-    const double R = g.Rc[i], Z = g.tc[j] * g.Rc[i];
+    const double R = g.Rc[i], iR = g.iRc[i], Z = g.tc[j] * g.Rc[i];
     const Prim P = {rho[t], v[3 * t], v[3 * t + 1], v[3 * t + 2]};
     const double Q[4] = {P.r, P.r * P.vR, P.r * P.vp * R, P.r * P.vZ};
     const Prim Ph = {rh[t], vh[3 * t], vh[3 * t + 1], vh[3 * t + 2]};
     double S[4];
-    sources(Ph, R, Z, g.GM, S);
-    const double f = dt / g.V[c];
+    sources(Ph, R, iR, Z, g.om2[c], S);
+    const double f = dt * g.iV[c];
     double Qd[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) Qd[k] = (Q[k] - f * FA[k]) + dt * S[k];
-    const Prim N1 = primitive(Qd, R);
-    const double w = dt / (dt + stop_time(g, gas, c, s));
+    const Prim N1 = primitive(Qd, iR);
+    const double w = dt / (dt + gas.tsf[c] * g.s[s]);
     const double *vg = gas.v_g + 3 * c;
     rho[t] = N1.r;
     v[3 * t] = N1.vR - w * (N1.vR - vg[0]);
@@ -369,6 +399,7 @@ struct coag_tctx {
     double *tables = nullptr;             // all geometry arrays in one allocation
     TGeo geo{};
     double *rh = nullptr, *vh = nullptr;  // half-step state
+    double *gt = nullptr;                 // gas tables (GasT), refreshed by every step
     unsigned long long *red = nullptr;    // reduction scalars (dt, hmin) and a counter
     // scheduler workspace
     void *K = nullptr;
@@ -437,8 +468,9 @@ int coag_transport_create(const coag_tgrid *grid, int32_t N, const double *s, do
     // host geometry: every table in one array, in this order
     const long nRc = nr, nRe = nr + 1, ndR = nr, nRcone = nr, nRx = nr + 4, ntc = nz, nte = nz + 1,
                ntx = nz + 4, nV = (long)nr * nz, nAR = (long)(nr + 1) * nz,
-               nAt = (long)nr * (nz + 1), ns = N;
-    std::vector<double> h(nRc + nRe + ndR + nRcone + nRx + ntc + nte + ntx + nV + nAR + nAt + ns);
+               nAt = (long)nr * (nz + 1), ns = N, nirx = nr + 3, nitx = nz + 3, nnt = nz + 1;
+    std::vector<double> h(nRc + nRe + ndR + nRcone + nRx + ntc + nte + ntx + nV + nAR + nAt + ns +
+                          nRc + nirx + nitx + 2 * nnt + 2 * nV);
     double *p = h.data();
     double *Rc = p; p += nRc;
     double *Rev = p; p += nRe;
@@ -451,7 +483,14 @@ int coag_transport_create(const coag_tgrid *grid, int32_t N, const double *s, do
     double *V = p; p += nV;
     double *AR = p; p += nAR;
     double *At = p; p += nAt;
-    double *sv = p;
+    double *sv = p; p += ns;
+    double *iRc = p; p += nRc;
+    double *irx = p; p += nirx;
+    double *itx = p; p += nitx;
+    double *nRt = p; p += nnt;
+    double *nZt = p; p += nnt;
+    double *iV = p; p += nV;
+    double *om2 = p;
     for (int i = 0; i <= nr; ++i) Rev[i] = Re[i];
     for (int j = 0; j <= nz; ++j) tev[j] = te[j];
     for (int i = 0; i < nr; ++i) {
@@ -483,6 +522,22 @@ int coag_transport_create(const coag_tgrid *grid, int32_t N, const double *s, do
     for (int i = 0; i <= nr; ++i)
         for (int j = 0; j < nz; ++j) AR[(long)i * nz + j] = 2.0 * M_PI * Re[i] * Re[i] * (te[j + 1] - te[j]);
     for (int k = 0; k < N; ++k) sv[k] = s[k];
+    // reciprocals and normals the kernels would otherwise divide for per thread
+    for (int i = 0; i < nr; ++i) iRc[i] = 1.0 / Rc[i];
+    for (int k = 0; k < nirx; ++k) irx[k] = 1.0 / (Rx[k + 1] - Rx[k]);
+    for (int k = 0; k < nitx; ++k) itx[k] = 1.0 / (tx[k + 1] - tx[k]);
+    for (int j = 0; j <= nz; ++j) {
+        const double cj = 1.0 / sqrt(1.0 + te[j] * te[j]);
+        nRt[j] = -te[j] * cj;
+        nZt[j] = cj;
+    }
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nz; ++j) {
+            const long c = (long)i * nz + j;
+            const double R = Rc[i], Z = tc[j] * Rc[i], r2 = R * R + Z * Z;
+            iV[c] = 1.0 / V[c];
+            om2[c] = grid->GM / (r2 * sqrt(r2));
+        }
 
     coag_tctx *t = new coag_tctx();
     t->nr = nr;
@@ -496,6 +551,7 @@ int coag_transport_create(const coag_tgrid *grid, int32_t N, const double *s, do
     const long C = (long)nr * nz;
     if (hipMalloc(&t->tables, h.size() * sizeof(double)) != hipSuccess ||
         hipMalloc(&t->rh, (size_t)C * N * 4 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&t->gt, (size_t)(2 * C + nAR + nAt) * sizeof(double)) != hipSuccess ||
         hipMalloc(&t->red, 4 * sizeof(unsigned long long)) != hipSuccess) {
         coag_transport_destroy(t);
         return tfail(nullptr, COAG_ENOMEM, "coag_transport_create: device allocation failed");
@@ -521,7 +577,14 @@ int coag_transport_create(const coag_tgrid *grid, int32_t N, const double *s, do
     g.V = d; d += nV;
     g.AR = d; d += nAR;
     g.At = d; d += nAt;
-    g.s = d;
+    g.s = d; d += ns;
+    g.iRc = d; d += nRc;
+    g.irx = d; d += nirx;
+    g.itx = d; d += nitx;
+    g.nRt = d; d += nnt;
+    g.nZt = d; d += nnt;
+    g.iV = d; d += nV;
+    g.om2 = d;
     g.rho_m = rho_m;
     g.GM = grid->GM;
     g.Sc = grid->Sc;
@@ -534,6 +597,7 @@ void coag_transport_destroy(coag_tctx *t) {
     (void)hipDeviceSynchronize();
     (void)hipFree(t->tables);
     (void)hipFree(t->rh);
+    (void)hipFree(t->gt);
     (void)hipFree(t->red);
     (void)hipFree(t->K);
     (void)hipFree(t->nsub);
@@ -573,7 +637,11 @@ int coag_transport_step(coag_tctx *t, const coag_cells *cells, const double *v_g
     hipStream_t st = (hipStream_t)stream;
     const long waves = (long)t->nr * t->nz * ((t->N + 63) / 64);
     const dim3 grid((unsigned)((waves + kTBlock / 64 - 1) / (kTBlock / 64)));
-    const Gas gas = gas_of(cells, v_gas);
+    const long C = (long)t->nr * t->nz;
+    double *irg = t->gt, *tsf = irg + C, *KR = tsf + C, *Kt = KR + (long)(t->nr + 1) * t->nz;
+    hipLaunchKernelGGL(k_tr_prep, dim3((unsigned)((C + kTBlock - 1) / kTBlock)), dim3(kTBlock), 0,
+                       st, t->geo, gas_of(cells, v_gas), irg, tsf, KR, Kt);
+    const GasT gas{irg, tsf, KR, Kt, v_gas};
     hipLaunchKernelGGL(k_tr_half, grid, dim3(kTBlock), 0, st, t->geo, gas, rho, v, t->rh, t->vh, dt);
     hipLaunchKernelGGL(k_tr_full, grid, dim3(kTBlock), 0, st, t->geo, gas, rho, v, t->rh, t->vh, dt);
     THIP(t, hipGetLastError());
