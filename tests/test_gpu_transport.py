@@ -27,9 +27,9 @@ def _t(a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
 
 
-def _inputs(n_r, n_z, n_bins, fill=True):
+def _inputs(n_r, n_z, n_bins, fill=True, base="disc64x32_n100"):
     from paper_2402_18471_amd import disc
-    cfg = disc.scaled(disc.CONFIGS["disc64x32_n100"], n_r, n_z, n_bins)
+    cfg = disc.scaled(disc.CONFIGS[base], n_r, n_z, n_bins)
     s = np.geomspace(cfg.s_min, cfg.s_max, n_bins)
     d = disc.make_transport(cfg, s)
     if fill:
@@ -70,6 +70,18 @@ def test_transport_steps_match_the_oracle(shape):
     n_r, n_z, N = shape
     cfg, s, d = _inputs(n_r, n_z, N)
     _parity(shape, cfg, s, d, 2 if N > 100 else 3)
+
+
+def test_transport_step_matches_the_oracle_at_the_bench_size():
+    """One step of the full 256 x 128-cell, 150-species disc the bench times
+    (every bin filled), element by element against the oracle (about 16 s
+    of numpy)."""
+    from paper_2402_18471_amd import disc
+    cfg0 = disc.CONFIGS["disc256x128_n150"]
+    shape = (cfg0.n_r, cfg0.n_z, cfg0.n_bins)
+    cfg, s, d = _inputs(*shape, base="disc256x128_n150")
+    assert (cfg.n_r, cfg.n_z, cfg.n_bins) == shape
+    _parity(shape, cfg, s, d, 1)
 
 
 def test_subnormal_densities_match_the_oracle():
