@@ -669,6 +669,18 @@ def transport_leg(torch, config, steps=20, warmup=3, evolve_yr=10.0):
     out["evolve"] = {"t_end_yr": t_end / 3.15576e7, "wall_s": wall, **st,
                      "note": "coag_evolve: CFL transport steps, FP64 coagulation triggered by the "
                              "scheduler rule; wall time includes one host sync per transport step"}
+    # the same run with a dust-to-gas floor of 1e-20 per species: near-empty
+    # species move with the gas and stop setting the CFL step
+    eps = 1e-20
+    tf = TransportContext(d["R_edge"], d["t_edge"], s, rho_m=cfg.rho_m, GM=d["GM"], eps_floor=eps)
+    rho, v = t(d["rho"]), t(d["v"])
+    h = torch.zeros(C, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    st = tf.evolve(ctx, cells, vg, vf, rho, v, h, t_end)
+    torch.cuda.synchronize()
+    out["evolve_floor"] = {"eps_floor": eps, "t_end_yr": t_end / 3.15576e7,
+                           "wall_s": time.perf_counter() - w0, **st}
     return out
 
 

@@ -48,12 +48,17 @@ typedef struct coag_tctx coag_tctx;
 /* n_r >= 1, n_z >= 1; R_edge HOST [n_r + 1] increasing and > 0; t_edge HOST
    [n_z + 1] increasing with t_edge[0] = 0; GM = G M_* (cgs); Sc > 0 the
    Schmidt number (1 in the paper's runs); c_adv, c_diff the Courant numbers
-   of eqs. `dt_adv`, `dt_diff` (0.4 and 0.2 by default). */
+   of eqs. `dt_adv`, `dt_diff` (0.4 and 0.2 by default); eps_floor >= 0 the
+   dust-to-gas floor of each species (Secs. 2 and 7 speak of floor values
+   without giving them): a species whose density in a cell ends either stage
+   of a step below eps_floor rho_g takes the gas velocity there, its density
+   kept; 0 = no floor. */
 typedef struct {
     int32_t n_r, n_z;
     const double *R_edge;
     const double *t_edge;
     double GM, Sc, c_adv, c_diff;
+    double eps_floor;
 } coag_tgrid;
 
 /* Create a transport context on the current device for N species of grain

@@ -43,6 +43,9 @@ Readings where the paper leaves the discretisation open:
   the left or right state by its sign (eq. `Fdiffmom` read as F_diff times
   v_R, v_phi R, v_Z).
 * Primitives of an empty cell (rho <= 0): velocity 0.
+* Dust floor (optional, off by default): a species below eps_floor rho_g in
+  a cell at the end of either stage takes the gas velocity; its density is
+  kept, so mass stays conserved (`at_floor`).
 """
 from __future__ import annotations
 
@@ -295,9 +298,21 @@ def drag(v, v_g, ts, h):
 # ---------------------------------------------------------------------------
 # one step and the CFL time step
 # ---------------------------------------------------------------------------
-def step(g: Geometry, gas: Gas, s, rho_m, rho, v, dt):
+def at_floor(gas: Gas, rho, v, eps_floor):
+    """The dust floor (a reading: Sec. 2 and Sec. 7 speak of floor values of
+    the dust density and dust-to-gas ratio without giving them): a species
+    whose density in a cell is below eps_floor rho_g moves with the gas; its
+    density is kept.  eps_floor = 0: no floor."""
+    if eps_floor <= 0.0:
+        return v
+    low = rho < eps_floor * gas.rho_g[..., None]
+    return np.where(low[..., None], gas.v_g[:, :, None, :], v)
+
+
+def step(g: Geometry, gas: Gas, s, rho_m, rho, v, dt, eps_floor=0.0):
     """One transport step of dt from (rho [nr, nz, N], v [nr, nz, N, 3]);
-    returns the new (rho, v)."""
+    returns the new (rho, v).  With eps_floor > 0 the floor applies to the
+    state each of the two stages ends with."""
     Rq = g.Rc[:, None, None]
     ts = stopping_time(gas, s, rho_m)
     Q0 = conserved(rho, v, Rq)
@@ -306,12 +321,12 @@ def step(g: Geometry, gas: Gas, s, rho_m, rho, v, dt):
     Qs = Q0 - 0.5 * dt / V * flux_area(g, gas, rho, v, order=1)
     Qss = Qs + 0.5 * dt * sources(g, gas, rho, v)
     r_h, v_ss = primitive(Qss, Rq)
-    v_h = drag(v_ss, gas.v_g, ts, 0.5 * dt)
+    v_h = at_floor(gas, r_h, drag(v_ss, gas.v_g, ts, 0.5 * dt), eps_floor)
     # (v)-(viii): second-order fluxes at t^{n+1/2}, full update from Q^n
     Qd = Q0 - dt / V * flux_area(g, gas, r_h, v_h, order=2)
     Qdd = Qd + dt * sources(g, gas, r_h, v_h)
     r1, v_dd = primitive(Qdd, Rq)
-    v1 = drag(v_dd, gas.v_g, ts, dt)
+    v1 = at_floor(gas, r1, drag(v_dd, gas.v_g, ts, dt), eps_floor)
     return r1, v1
 
 

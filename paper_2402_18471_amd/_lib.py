@@ -46,7 +46,7 @@ class Tol(ct.Structure):
 class TGrid(ct.Structure):
     _fields_ = [("n_r", ct.c_int32), ("n_z", ct.c_int32), ("R_edge", _dp), ("t_edge", _dp),
                 ("GM", ct.c_double), ("Sc", ct.c_double), ("c_adv", ct.c_double),
-                ("c_diff", ct.c_double)]
+                ("c_diff", ct.c_double), ("eps_floor", ct.c_double)]
 
 
 class EvolveStats(ct.Structure):

@@ -266,16 +266,19 @@ class TransportContext:
     """coag_transport_create / destroy (include/coag_transport.h): the dust
     transport step of the dynamics solver on an (R, t = Z/R) grid of n_r x n_z
     cells for the N species of radii s, and the scheduler coupling it to a
-    CoagContext.  Marshalling only: the step runs in the library's kernels."""
+    CoagContext.  Marshalling only: the step runs in the library's kernels.
+    eps_floor: the dust-to-gas floor of each species (0: none)."""
 
-    def __init__(self, R_edge, t_edge, s, rho_m=1.67, GM=0.0, Sc=1.0, c_adv=0.4, c_diff=0.2):
+    def __init__(self, R_edge, t_edge, s, rho_m=1.67, GM=0.0, Sc=1.0, c_adv=0.4, c_diff=0.2,
+                 eps_floor=0.0):
         self.R_edge = np.ascontiguousarray(R_edge, dtype=np.float64)
         self.t_edge = np.ascontiguousarray(t_edge, dtype=np.float64)
         self.s = np.ascontiguousarray(s, dtype=np.float64)
         self.n_r, self.n_z, self.N = len(self.R_edge) - 1, len(self.t_edge) - 1, len(self.s)
         self.C = self.n_r * self.n_z
         dp = lambda a: a.ctypes.data_as(L._dp)
-        g = L.TGrid(self.n_r, self.n_z, dp(self.R_edge), dp(self.t_edge), GM, Sc, c_adv, c_diff)
+        g = L.TGrid(self.n_r, self.n_z, dp(self.R_edge), dp(self.t_edge), GM, Sc, c_adv, c_diff,
+                    eps_floor)
         h = ct.c_void_p()
         self._lib = L.load()
         L.check_t(self._lib.coag_transport_create(ct.byref(g), self.N, dp(self.s), rho_m,

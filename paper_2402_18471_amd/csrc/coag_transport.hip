@@ -62,6 +62,7 @@ struct TGeo {
     const double *iV;        // [nr * nz] 1 / V
     const double *om2;       // [nr * nz] GM / r^3 at the cell centre
     double rho_m, GM, Sc;
+    double eps_floor;        // dust-to-gas floor (0: none)
 };
 
 // per-step tables of the gas (k_tr_prep): 1 / rho_g, the stopping time per
@@ -73,6 +74,7 @@ struct GasT {
     const double *KR;        // [(nr + 1) * nz] cylinder faces
     const double *Kt;        // [nr * (nz + 1)] cone faces
     const double *v_g;       // [C][3]
+    const double *rho_g;     // [C]
 };
 
 struct Gas {
@@ -296,10 +298,12 @@ __global__ __launch_bounds__(kTBlock) void k_tr_half(TGeo g, GasT gas, const dou
     Prim H = primitive(Qs, iR);
     const double hd = 0.5 * dt, w = hd / (hd + gas.tsf[c] * g.s[s]);
     const double *vg = gas.v_g + 3 * c;
+    // below the floor the species moves with the gas
+    const bool fl = g.eps_floor > 0.0 && H.r < g.eps_floor * gas.rho_g[c];
     rh[t] = H.r;
-    vh[3 * t] = H.vR - w * (H.vR - vg[0]);
-    vh[3 * t + 1] = H.vp - w * (H.vp - vg[1]);
-    vh[3 * t + 2] = H.vZ - w * (H.vZ - vg[2]);
+    vh[3 * t] = fl ? vg[0] : H.vR - w * (H.vR - vg[0]);
+    vh[3 * t + 1] = fl ? vg[1] : H.vp - w * (H.vp - vg[1]);
+    vh[3 * t + 2] = fl ? vg[2] : H.vZ - w * (H.vZ - vg[2]);
 }
 
 // Stages (v)-(viii): second-order fluxes at t^{n+1/2}, full update from t^n,
@@ -328,10 +332,11 @@ __global__ __launch_bounds__(kTBlock) void k_tr_full(TGeo g, GasT gas, double *r
     const Prim N1 = primitive(Qd, iR);
     const double w = dt / (dt + gas.tsf[c] * g.s[s]);
     const double *vg = gas.v_g + 3 * c;
+    const bool fl = g.eps_floor > 0.0 && N1.r < g.eps_floor * gas.rho_g[c];
     rho[t] = N1.r;
-    v[3 * t] = N1.vR - w * (N1.vR - vg[0]);
-    v[3 * t + 1] = N1.vp - w * (N1.vp - vg[1]);
-    v[3 * t + 2] = N1.vZ - w * (N1.vZ - vg[2]);
+    v[3 * t] = fl ? vg[0] : N1.vR - w * (N1.vR - vg[0]);
+    v[3 * t + 1] = fl ? vg[1] : N1.vp - w * (N1.vp - vg[1]);
+    v[3 * t + 2] = fl ? vg[2] : N1.vZ - w * (N1.vZ - vg[2]);
 }
 
 // positive doubles order like their bit patterns: the minimum via atomicMin on them
@@ -450,9 +455,10 @@ int coag_transport_create(const coag_tgrid *grid, int32_t N, const double *s, do
         return tfail(nullptr, COAG_EINVAL, "coag_transport_create: n_r = %d, n_z = %d, N = %d", nr,
                      nz, N);
     if (!(rho_m > 0.0) || !(grid->Sc > 0.0) || !(grid->c_adv > 0.0) || !(grid->c_diff > 0.0) ||
-        !(grid->GM >= 0.0))
+        !(grid->GM >= 0.0) || !(grid->eps_floor >= 0.0) || !std::isfinite(grid->eps_floor))
         return tfail(nullptr, COAG_EINVAL,
-                     "coag_transport_create: need rho_m, Sc, c_adv, c_diff > 0 and GM >= 0");
+                     "coag_transport_create: need rho_m, Sc, c_adv, c_diff > 0, GM >= 0 and a "
+                     "finite eps_floor >= 0");
     const double *Re = grid->R_edge, *te = grid->t_edge;
     if (!(Re[0] > 0.0) || te[0] != 0.0)
         return tfail(nullptr, COAG_EINVAL, "coag_transport_create: need R_edge[0] > 0, t_edge[0] = 0");
@@ -588,6 +594,7 @@ int coag_transport_create(const coag_tgrid *grid, int32_t N, const double *s, do
     g.rho_m = rho_m;
     g.GM = grid->GM;
     g.Sc = grid->Sc;
+    g.eps_floor = grid->eps_floor;
     *out = t;
     return COAG_OK;
 }
@@ -641,7 +648,7 @@ int coag_transport_step(coag_tctx *t, const coag_cells *cells, const double *v_g
     double *irg = t->gt, *tsf = irg + C, *KR = tsf + C, *Kt = KR + (long)(t->nr + 1) * t->nz;
     hipLaunchKernelGGL(k_tr_prep, dim3((unsigned)((C + kTBlock - 1) / kTBlock)), dim3(kTBlock), 0,
                        st, t->geo, gas_of(cells, v_gas), irg, tsf, KR, Kt);
-    const GasT gas{irg, tsf, KR, Kt, v_gas};
+    const GasT gas{irg, tsf, KR, Kt, v_gas, cells->rho_g};
     hipLaunchKernelGGL(k_tr_half, grid, dim3(kTBlock), 0, st, t->geo, gas, rho, v, t->rh, t->vh, dt);
     hipLaunchKernelGGL(k_tr_full, grid, dim3(kTBlock), 0, st, t->geo, gas, rho, v, t->rh, t->vh, dt);
     THIP(t, hipGetLastError());

@@ -104,9 +104,10 @@ def test_transport_create_rejects_bad_grids_on_the_host(L):
     s = np.array([1e-4, 1e-3])
     h = ct.c_void_p()
 
-    def create(R_, t_, s_=s, N=2, rho_m=1.6, GM=1.0, Sc=1.0, ca=0.4, cd=0.2, nr=None, nz=None):
+    def create(R_, t_, s_=s, N=2, rho_m=1.6, GM=1.0, Sc=1.0, ca=0.4, cd=0.2, nr=None, nz=None,
+               ef=0.0):
         g = L.TGrid(len(R_) - 1 if nr is None else nr, len(t_) - 1 if nz is None else nz,
-                    dp(R_), dp(t_), GM, Sc, ca, cd)
+                    dp(R_), dp(t_), GM, Sc, ca, cd, ef)
         return lib.coag_transport_create(ct.byref(g), N, dp(s_), rho_m, ct.byref(h))
 
     bad = [dict(R_=np.array([1.0, 1.0, 3.0]), t_=t),          # R not increasing
@@ -117,7 +118,8 @@ def test_transport_create_rejects_bad_grids_on_the_host(L):
            dict(R_=R, t_=t, N=0), dict(R_=R, t_=t, N=1024),
            dict(R_=R, t_=t, rho_m=0.0), dict(R_=R, t_=t, GM=-1.0), dict(R_=R, t_=t, Sc=0.0),
            dict(R_=R, t_=t, ca=0.0), dict(R_=R, t_=t, cd=-1.0), dict(R_=R, t_=t, nr=0),
-           dict(R_=R, t_=t, nz=0)]
+           dict(R_=R, t_=t, nz=0), dict(R_=R, t_=t, ef=-1e-20), dict(R_=R, t_=t, ef=np.inf),
+           dict(R_=R, t_=t, ef=np.nan)]
     for kw in bad:
         assert create(**kw) == L.COAG_EINVAL, kw
         assert h.value is None

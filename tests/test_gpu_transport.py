@@ -49,9 +49,10 @@ def _oracle(cfg, s, d):
     return T, g, gas
 
 
-def _ctx(cfg, s, d):
+def _ctx(cfg, s, d, eps_floor=0.0):
     from paper_2402_18471_amd.coag import TransportContext
-    return TransportContext(d["R_edge"], d["t_edge"], s, rho_m=cfg.rho_m, GM=d["GM"])
+    return TransportContext(d["R_edge"], d["t_edge"], s, rho_m=cfg.rho_m, GM=d["GM"],
+                            eps_floor=eps_floor)
 
 
 def _close(rho_g, v_g, rho_o, v_o):
@@ -96,10 +97,27 @@ def test_subnormal_densities_match_the_oracle():
     _parity((n_r, n_z, N), cfg, s, d, 2)
 
 
-def _parity(shape, cfg, s, d, n_steps):
+def test_floor_species_match_the_oracle():
+    """The dust floor: three species at 1e-30 of the gas density with
+    meaningless speeds (1e7 cm/s), eps_floor = 1e-20: both sides give them
+    the gas velocity at the end of each stage, and the later CFL steps come
+    from the other species."""
+    n_r, n_z, N = 24, 12, 12
+    cfg, s, d = _inputs(n_r, n_z, N)
+    rng = np.random.default_rng(5)
+    rho = d["rho"].reshape(-1, N)
+    rho[:, 9:] = 1e-30 * d["cells"]["rho_g"][:, None]
+    v = d["v"].reshape(-1, N, 3)
+    v[:, 9:, :] = rng.normal(0.0, 1e7, (rho.shape[0], 3, 3))
+    v_after = _parity((n_r, n_z, N), cfg, s, d, 3, eps_floor=1e-20)
+    vg = d["v_gas"].reshape(-1, 1, 3)
+    assert np.array_equal(v_after.reshape(-1, N, 3)[:, 9:, :], np.broadcast_to(vg, (rho.shape[0], 3, 3)))
+
+
+def _parity(shape, cfg, s, d, n_steps, eps_floor=0.0):
     n_r, n_z, N = shape
     T, g, gas = _oracle(cfg, s, d)
-    tc = _ctx(cfg, s, d)
+    tc = _ctx(cfg, s, d, eps_floor)
     cells = {k: _t(v) for k, v in d["cells"].items()}
     rho, v, vg = _t(d["rho"]), _t(d["v"]), _t(d["v_gas"])
     ro = d["rho"].reshape(n_r, n_z, N).copy()
@@ -113,13 +131,14 @@ def _parity(shape, cfg, s, d, n_steps):
         assert dt_g == pytest.approx(dt_o, rel=1e-14 if k == 0 else 1e-9), (k, dt_g, dt_o)
         # both sides step by the oracle's step size
         tc.step(cells, vg, rho, v, dt_o)
-        ro, vo = T.step(g, gas, s, cfg.rho_m, ro, vo, dt_o)
+        ro, vo = T.step(g, gas, s, cfg.rho_m, ro, vo, dt_o, eps_floor=eps_floor)
         torch.cuda.synchronize()
         er, ev = _close(rho.cpu().numpy(), v.cpu().numpy().reshape(-1, N, 3),
                         ro.reshape(-1, N), vo.reshape(-1, N, 3))
         print(f"shape {shape} step {k}: density {er:.3g}, velocity {ev:.3g} of the bar")
         assert bool(torch.isfinite(v).all()) and bool(torch.isfinite(rho).all())
         assert er <= 1.0 and ev <= 1.0
+    return v.cpu().numpy()
 
 
 def test_transport_conserves_mass_on_the_gpu():

@@ -231,3 +231,51 @@ def test_cfl_limits():
     gas = _gas(g, nu=3.0)
     v[...] = 0.0
     assert T.cfl_dt(g, gas, v) == pytest.approx(0.2 * (0.1 * g.Rc[0]) ** 2 / 3.0, rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# the dust floor (a reading: floor values are mentioned, not specified)
+# ---------------------------------------------------------------------------
+def test_floor_species_move_with_the_gas_and_stop_limiting_the_step():
+    """A near-empty large-grain species (1e-30 of the gas density) with
+    meaningless speeds: without a floor it keeps limiting the CFL step;
+    with eps_floor = 1e-20 it ends each stage with the gas velocity, the
+    species above the floor are untouched wherever their stencil (two cells
+    each way) holds no floored cell (species do not interact in the transport
+    step; floored neighbours change the limited slopes), mass is still
+    conserved, and the next CFL step is set by the physical species.
+    eps_floor = 0 is the step without a floor."""
+    rng = np.random.default_rng(19)
+    nr, nz, N = 20, 12, 4
+    g = _grid(nr, nz, log=True)
+    gas = _gas(g, nu=0.05, GM=0.5)
+    gas.rho_g = rng.uniform(0.5, 2.0, (nr, nz))
+    gas.c_s = rng.uniform(0.5, 1.0, (nr, nz))
+    gas.v_g = rng.normal(0.0, 0.1, (nr, nz, 3))
+    s = np.array([1e-3, 1e-2, 1e-1, 1.0])
+    rho = rng.uniform(0.1, 1.0, (nr, nz, N))
+    rho[..., 3] = 1e-30 * gas.rho_g
+    rho[:5] = rho[-5:] = 0.0
+    rho[:, -5:] = 0.0
+    v = rng.normal(0.0, 0.3, (nr, nz, N, 3))
+    v[..., 3, :] = rng.normal(0.0, 1e3, (nr, nz, 3))
+    eps = 1e-20
+    m0 = np.sum(g.V[..., None] * rho)
+    dt = T.cfl_dt(g, gas, v)
+    r0, v0 = T.step(g, gas, s, 1.6, rho, v, dt)
+    r00, v00 = T.step(g, gas, s, 1.6, rho, v, dt, eps_floor=0.0)
+    assert np.array_equal(r0, r00) and np.array_equal(v0, v00)
+    r1, v1 = T.step(g, gas, s, 1.6, rho, v, dt, eps_floor=eps)
+    low = r1 < eps * gas.rho_g[..., None]
+    assert np.all(low[..., 3]) and not np.all(low[..., :3])
+    assert np.array_equal(v1[low], np.broadcast_to(gas.v_g[:, :, None, :], v1.shape)[low])
+    # cells 7..12 in R, 0..4 in Z: every cell within two of them is filled
+    inner = (slice(7, 13), slice(0, 5), slice(0, 3))
+    assert np.all(rho[5:15, :7, :3] > 0.0)
+    assert np.array_equal(r1[inner], r0[inner]) and np.array_equal(v1[inner], v0[inner])
+    assert np.all(r1 >= 0.0)
+    assert abs(np.sum(g.V[..., None] * r1) - m0) <= 1e-14 * m0
+    # the next step: limited by the near-empty species without the floor only
+    assert T.cfl_dt(g, gas, v1) > 100.0 * T.cfl_dt(g, gas, v0)
+    phys = T.cfl_dt(g, gas, np.where(low[..., None], 0.0, v1))
+    assert T.cfl_dt(g, gas, v1) == pytest.approx(phys, rel=0.5)
