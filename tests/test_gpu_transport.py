@@ -179,8 +179,8 @@ def test_transport_rejects_bad_steps():
     assert torch.equal(rho, before)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "split"])
-def test_evolve_follows_the_scheduler_rule(prec):
+@pytest.mark.parametrize("prec,eps_floor", [("fp64", 0.0), ("split", 0.0), ("fp64", 1e-20)])
+def test_evolve_follows_the_scheduler_rule(prec, eps_floor):
     """coag_evolve against the rule written out with the library's own calls:
     dt = CFL step clipped to what is left; transport step; when the time since
     the last coagulation update reaches the smallest last sub-step of the
@@ -194,7 +194,7 @@ def test_evolve_follows_the_scheduler_rule(prec):
     m, me, s = coag_mass_grid(N, cfg.s_min, cfg.s_max, rho_m=cfg.rho_m)
     d = disc.make_transport(cfg, s)
     ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
-    tc = _ctx(cfg, s, d)
+    tc = _ctx(cfg, s, d, eps_floor)
     cells = {k: _t(v) for k, v in d["cells"].items()}
     vg, vf = _t(d["v_gas"]), _t(d["v_frag"])
     p = L.PREC_SPLIT_BF16 if prec == "split" else L.PREC_FP64
