@@ -45,6 +45,11 @@ KERNEL_FILES = [os.path.join("csrc", f) for f in ("coag_batch.hip", "coag_batch.
                                                     "coag_batch_common.h", "coag_launch.h",
                                                     "coag_device.h")] + ["build.py"]
 COUNTERS = os.path.join(ROOT, "profiles", "kernel_counters.json")
+# every file the transport kernels are built from, and their counter summary
+TRANSPORT_FILES = [os.path.join("csrc", f) for f in ("coag_transport.hip", "coag_rate.h",
+                                                    "coag_launch.h", "coag_device.h")] + [
+    os.path.join("..", "include", f) for f in ("coag.h", "coag_transport.h")] + ["build.py"]
+TR_COUNTERS = os.path.join(ROOT, "profiles", "transport_counters.json")
 
 
 def progress(msg):
@@ -91,6 +96,13 @@ def parse():
     ap.add_argument("--evolve-calls", type=int, default=20)
     ap.add_argument("--evolve-ckpt", type=int, default=20)
     ap.add_argument("--evolve-prec", choices=("fp64", "split"), default="split")
+    ap.add_argument("--summarize-transport-counters", nargs=3,
+                    metavar=("OUT_JSON", "FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU work: write the transport kernels' counter summary (the "
+                         "transport roofline's traffic is read from it) from a FETCH_SIZE and a "
+                         "WRITE_SIZE pass of rocprofv3 over a 'bench.py --steps 1 --warmup 1 "
+                         "--no-cpu-baseline --no-adjoint --no-vertical --no-split "
+                         "--calibrate-copy' run")
     ap.add_argument("--summarize-counters", nargs="+",
                     metavar="OUT_JSON BENCH_LOG TRACE_CSV PMC_CSV",
                     help="no GPU work: write the per-kernel counter summary (the roofline's "
@@ -322,12 +334,66 @@ def summarize_counters(out_json, bench_log, trace_csv, *pmc_csvs):
     print(json.dumps(out))
 
 
-def kernel_shas():
-    """SHA-256 of every file the batched step's code object is built from."""
+def kernel_shas(files=None):
+    """SHA-256 of every file the batched step's code object (or the files
+    given, paths relative to the package) is built from."""
     import hashlib
     pkg = os.path.join(ROOT, "paper_2402_18471_amd")
     return {f: hashlib.sha256(open(os.path.join(pkg, f), "rb").read()).hexdigest()
-            for f in KERNEL_FILES}
+            for f in (KERNEL_FILES if files is None else files)}
+
+
+def summarize_transport_counters(out_json, fetch_csv, write_csv):
+    """Counter summary of the transport kernels from a FETCH_SIZE and a
+    WRITE_SIZE pass of rocprofv3 over one 'bench.py --steps 1 --warmup 1
+    --no-cpu-baseline --no-adjoint --no-vertical --no-split --calibrate-copy'
+    run: per kernel the mean over its launches (all on the bench disc), in
+    bytes, scaled by what the counters read for the final 1 GiB device copy;
+    the step's bytes are those of k_tr_prep, k_tr_half and k_tr_full."""
+    import csv
+    vals = {}
+    for path in (fetch_csv, write_csv):
+        for r in csv.DictReader(open(path)):
+            k = _kernel_short(r["Kernel_Name"])
+            if k == "__amd_rocclr_copyBuffer":
+                k = (k, int(r["Grid_Size"]))
+            vals.setdefault((k, r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+    cal = {c: max(max(v) for (k, cn), v in vals.items()
+                  if isinstance(k, tuple) and cn == c) for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    fac = {c: (1 << 30) / (cal[c] * 1024.0) for c in cal}
+    kern = {}
+    for (k, cn), v in vals.items():
+        if isinstance(k, str) and k.startswith("k_tr_") and cn in fac:
+            d = kern.setdefault(k, {"launches": len(v)})
+            d["fetch_bytes" if cn == "FETCH_SIZE" else "write_bytes"] = (
+                sum(v) / len(v) * 1024.0 * fac[cn])
+    step = sum(kern[k][b] for k in ("k_tr_prep", "k_tr_half", "k_tr_full")
+               for b in ("fetch_bytes", "write_bytes"))
+    out = {"kernel_sources_sha256": kernel_shas(TRANSPORT_FILES),
+           "workload": "disc256x128_n150 transport (bench.py --steps 1 --warmup 1 "
+                       "--no-cpu-baseline --no-adjoint --no-vertical --no-split --calibrate-copy)",
+           "calibration": {"copy_bytes": 1 << 30, "FETCH_SIZE_KiB": cal["FETCH_SIZE"],
+                           "WRITE_SIZE_KiB": cal["WRITE_SIZE"], "fetch_factor": fac["FETCH_SIZE"],
+                           "write_factor": fac["WRITE_SIZE"]},
+           "kernels": kern, "step_bytes": step}
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({"step_bytes": step, "kernels": kern}))
+
+
+def transport_traffic():
+    """HBM bytes of one transport step on the bench disc from the committed
+    counter summary, or None when there is none or any file the transport
+    kernels are built from has changed since the counters were taken."""
+    try:
+        with open(TR_COUNTERS) as f:
+            c = json.load(f)
+        shas = kernel_shas(TRANSPORT_FILES)
+    except OSError:
+        return None
+    if c.get("kernel_sources_sha256") != shas:
+        return None
+    return float(c["step_bytes"])
 
 
 def profiled_traffic(rhs_per_launch, kind):
@@ -650,11 +716,13 @@ def transport_leg(torch, config, steps=20, warmup=3, evolve_yr=10.0):
             dts.append(dt)
     step_ms = float(np.mean(ms))
     byts = 160.0 * C * N
+    tb = transport_traffic() if config == "disc256x128_n150" else None
     out = {"workload": f"{config} transport", "cells": C, "species": N, "steps": steps,
            "step_ms": step_ms, "cell_species_updates_per_s": C * N / (step_ms * 1e-3),
            "cfl_dt_yr": float(np.mean(dts)) / 3.15576e7,
            "roofline": {"bound": "hbm", "achieved": byts / (step_ms * 1e-3) / 1e9, "peak": 8000.0,
                         "unit": "GB/s", "frac": byts / (step_ms * 1e-3) / 1e9 / 8000.0,
+                        "traffic": None if tb is None else tb / 1e9, "traffic_unit": "GB per step",
                         "algorithmic_bytes": "160 B per (cell, species) per step"}}
     ctx = coag_create(m, me, s, rho_m=cfg.rho_m)
     rho, v = t(d["rho"]), t(d["v"])
@@ -688,6 +756,9 @@ def main():
     args = parse()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
+        return
+    if args.summarize_transport_counters:
+        summarize_transport_counters(*args.summarize_transport_counters)
         return
     if args.evolve:
         evolve(args)
