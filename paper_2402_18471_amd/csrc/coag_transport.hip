@@ -8,9 +8,10 @@
 // Each thread evaluates the fluxes through its own cell's four faces (a face
 // shared by two cells is evaluated by both, from the same operands in the
 // same order, hence to the same bits: the update stays conservative without
-// a separate face pass or atomics).  The step is bound by FP64 vector issue:
-// per (cell, species) the two kernels evaluate six face fluxes with their
-// square roots and, in the second stage, twelve limited slopes; whatever
+// a separate face pass or atomics).  The step is held by the issue and
+// latency of its FP64 vector work: per (cell, species) the two kernels
+// evaluate eight face fluxes (four per stage) with their square roots and,
+// in the second stage, six limited slopes of four primitives each; whatever
 // depends on the cell alone (geometry, gas, diffusion coefficients of the
 // faces, reciprocals) comes from tables, read through the scalar cache.
 #include <hip/hip_runtime.h>
