@@ -105,14 +105,16 @@ typedef struct {
    CFL step, clipped to what remains; transport step; advance the clock; if the
    time since the last coagulation update reaches the trigger, or t_end is
    reached, run one coagulation update over that time (rates from the current
-   velocities, 16-cell-blocked FP64, then an ADAPTIVE coag_step under tol, h
-   carried in h) and set the trigger to the smallest last sub-step h of the
+   velocities, then an ADAPTIVE coag_step under tol, h carried in h) and set
+   the trigger to the smallest last sub-step h of the
    cells }.  The first trigger is the smallest h on entry (0: the first step
    triggers).  ctx: a coagulation context with the same N and grain radii;
    v_frag DEVICE [C]; h DEVICE [C] in/out; tol: mode must be COAG_ADAPTIVE,
    prec COAG_PREC_FP64 or COAG_PREC_SPLIT_BF16 (rates in the matching blocked
-   layout); max_steps caps the transport steps (COAG_EINVAL past it, state as
-   reached).  Synchronises the stream once per transport step (to read dt).
+   layout where the batched step applies to the context's grid; elsewhere
+   FP64 runs the per-cell step on [C][P] rates, and split precision returns
+   COAG_ENOTSUP before any work); max_steps caps the transport steps
+   (COAG_EINVAL past it, state as reached).  Synchronises the stream once per transport step (to read dt).
    stats may be NULL. */
 int coag_evolve(coag_ctx *ctx, coag_tctx *t, int64_t C, const coag_cells *cells,
                 const double *v_gas, const double *v_frag, double *rho, double *v, double *h,

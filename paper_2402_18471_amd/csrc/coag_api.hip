@@ -96,6 +96,11 @@ static int set_device(coag_ctx *ctx) {
 // the bin count of a context, for the transport scheduler (coag_transport.hip)
 namespace coag {
 int ctx_bins(const ::coag_ctx *ctx) { return ctx->N; }
+// whether coag_step takes 16-cell-blocked rates in this precision (0 FP64,
+// 1 split): the batched step applies to the grid, and for FP64 is selected
+bool ctx_blocked(const ::coag_ctx *ctx, int prec) {
+    return batch_available(ctx->T, ctx->B) && (prec == 1 || ctx->batch_fp64);
+}
 }  // namespace coag
 
 extern "C" {

@@ -33,8 +33,10 @@
 
 namespace coag {
 
-// number of bins of a coagulation context (coag_api.hip)
+// number of bins of a coagulation context, and whether its step takes
+// 16-cell-blocked rates in a precision (coag_api.hip)
 int ctx_bins(const ::coag_ctx *ctx);
+bool ctx_blocked(const ::coag_ctx *ctx, int prec);
 
 namespace {
 
@@ -677,9 +679,19 @@ int coag_evolve(coag_ctx *ctx, coag_tctx *t, int64_t C, const coag_cells *cells,
     hipStream_t st = (hipStream_t)stream;
     const int N = t->N;
     const bool split = tol->prec == COAG_PREC_SPLIT_BF16;
+    // blocked rates where the batched step applies; otherwise (FP64 only) the
+    // per-cell step with [C][P] rates
+    const bool blocked = ctx_blocked(ctx, split ? 1 : 0);
+    if (split && !blocked)
+        return tfail(t, COAG_ENOTSUP,
+                     "coag_evolve: split precision needs the batched step, which this "
+                     "context's grid does not allow (N >= 16 bins whose products of each row "
+                     "fit a 16-bin window)");
     const long m = N >> 1;
     const long SL = (N & 1) ? (m + 1) * (m + 1) : m * (m + 1);
-    const size_t kb = (size_t)64 * SL * ((C + 15) / 16) * (split ? 4 : 8);
+    const long P = (long)N * (N + 1) / 2;
+    const size_t kb = blocked ? (size_t)64 * SL * ((C + 15) / 16) * (split ? 4 : 8)
+                              : (size_t)2 * C * P * sizeof(double);
     if (kb > t->K_bytes) {
         (void)hipFree(t->K);
         t->K = nullptr;
@@ -697,7 +709,7 @@ int coag_evolve(coag_ctx *ctx, coag_tctx *t, int64_t C, const coag_cells *cells,
         t->ws_cells = C;
     }
     coag_tol tl = *tol;
-    tl.rates_layout = split ? COAG_RATES_BLK32 : COAG_RATES_BLK64;
+    tl.rates_layout = !blocked ? COAG_RATES_CP64 : split ? COAG_RATES_BLK32 : COAG_RATES_BLK64;
     const dim3 cg((unsigned)((C + kTBlock - 1) / kTBlock));
     // the trigger: smallest positive h of the cells (0 if none), and the failed cells
     auto trigger = [&](double &hmin, int &nbad, bool with_status) -> int {
@@ -740,9 +752,11 @@ int coag_evolve(coag_ctx *ctx, coag_tctx *t, int64_t C, const coag_cells *cells,
         time = last ? t_end : time + dt;
         since += dt;
         if (since >= trig || last) {
-            rc = coag_rates_blocked(ctx, C, cells, v, v_frag, split ? 1 : 0, t->K, stream);
+            double *Kc = (double *)t->K, *Kf = blocked ? nullptr : Kc + C * P;
+            rc = blocked ? coag_rates_blocked(ctx, C, cells, v, v_frag, split ? 1 : 0, t->K, stream)
+                         : coag_rates(ctx, C, cells, v, v_frag, Kc, Kf, stream);
             if (rc) return tfail(t, rc, "coag_evolve: rates: %s", coag_last_error(ctx));
-            rc = coag_step(ctx, C, rho, t->K, nullptr, since, h, &tl, t->nsub, nullptr, nullptr,
+            rc = coag_step(ctx, C, rho, t->K, Kf, since, h, &tl, t->nsub, nullptr, nullptr,
                            t->status, stream);
             if (rc) return tfail(t, rc, "coag_evolve: step: %s", coag_last_error(ctx));
             ++calls;
