@@ -108,7 +108,8 @@ typedef struct {
    velocities, then an ADAPTIVE coag_step under tol, h carried in h) and set
    the trigger to the smallest last sub-step h of the
    cells }.  The first trigger is the smallest h on entry (0: the first step
-   triggers).  ctx: a coagulation context with the same N and grain radii;
+   triggers).  ctx: a coagulation context with the same N and grain radii,
+   for the volume kernel (a vertically integrated one: COAG_EINVAL);
    v_frag DEVICE [C]; h DEVICE [C] in/out; tol: mode must be COAG_ADAPTIVE,
    prec COAG_PREC_FP64 or COAG_PREC_SPLIT_BF16 (rates in the matching blocked
    layout where the batched step applies to the context's grid; elsewhere

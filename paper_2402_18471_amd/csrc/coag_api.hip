@@ -101,6 +101,8 @@ int ctx_bins(const ::coag_ctx *ctx) { return ctx->N; }
 bool ctx_blocked(const ::coag_ctx *ctx, int prec) {
     return batch_available(ctx->T, ctx->B) && (prec == 1 || ctx->batch_fp64);
 }
+// whether the context takes the vertically integrated kernel
+bool ctx_vertical(const ::coag_ctx *ctx) { return ctx->T.vertical != 0; }
 }  // namespace coag
 
 extern "C" {

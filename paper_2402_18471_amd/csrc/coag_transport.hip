@@ -37,6 +37,7 @@ namespace coag {
 // 16-cell-blocked rates in a precision (coag_api.hip)
 int ctx_bins(const ::coag_ctx *ctx);
 bool ctx_blocked(const ::coag_ctx *ctx, int prec);
+bool ctx_vertical(const ::coag_ctx *ctx);
 
 namespace {
 
@@ -671,6 +672,10 @@ int coag_evolve(coag_ctx *ctx, coag_tctx *t, int64_t C, const coag_cells *cells,
     if (ctx_bins(ctx) != t->N)
         return tfail(t, COAG_EINVAL, "coag_evolve: %d bins in the coagulation context, %d species",
                      ctx_bins(ctx), t->N);
+    if (ctx_vertical(ctx))
+        return tfail(t, COAG_EINVAL,
+                     "coag_evolve: the transport carries volume densities; the coagulation "
+                     "context takes the vertically integrated kernel's surface densities");
     if (!(t_end > 0.0) || !std::isfinite(t_end) || max_steps < 1)
         return tfail(t, COAG_EINVAL, "coag_evolve: t_end = %g, max_steps = %lld", t_end,
                      (long long)max_steps);

@@ -292,7 +292,8 @@ def test_a_disc_at_rest_has_no_cfl_limit():
 
 def test_evolve_rejects_bad_arguments():
     """coag_evolve's checks: t_end and max_steps, a coagulation context with
-    another bin count, a precision it does not take, split precision on a grid
+    another bin count or of the vertically integrated kernel, a precision it
+    does not take, split precision on a grid
     the batched step does not cover (all before any work); and the step cap,
     which stops a run that needs more steps with COAG_EINVAL and its state
     finite (10 bins: FP64 runs the per-cell step)."""
@@ -326,6 +327,8 @@ def test_evolve_rejects_bad_arguments():
         assert code(t_end=t_end)[0] == L.COAG_EINVAL
     assert code(max_steps=0)[0] == L.COAG_EINVAL
     assert code(ctx=ctx_other)[0] == L.COAG_EINVAL
+    # a context of the vertically integrated kernel takes surface densities
+    assert code(ctx=coag_create(m, me, s, rho_m=cfg.rho_m, vertical=True))[0] == L.COAG_EINVAL
     assert code(prec=7)[0] == L.COAG_EINVAL
     # split precision needs the batched step, which 10 bins do not allow:
     # refused before any transport step
